@@ -1,0 +1,435 @@
+"""Pins of the oracle's operator, drivers and references (CPU only).
+
+Each test checks the oracle against something other than itself:
+
+* hand-worked rational examples (tests/golden/hand_examples.txt);
+* the special cases b = n (Bellman operator T, eq. (7)) and b = 1
+  (Gauss-Seidel operator F, Sec. II-D), written here as the textbook loops;
+* the closed form of one policy sweep B_{mu,b}: a block-triangular linear
+  system in processing order, solved with scipy's triangular solver;
+* J* by brute force over all policies (eq. (2)) and by LAPACK (eq. (4));
+* the lemmas of Sec. III-B: monotonicity, shift invariance, contraction,
+  fixed point, convergence, and the batch-size ordering (Theorem and
+  Corollary of Sec. III-B.2).
+"""
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from oracle import (CsrMDP, DenseMDP, brute_force_optimum, greedy, mb_sweep,
+                    modified_policy_iteration, policy_iteration, policy_value,
+                    q_values, row_sums, shifted_costs, sweep_permutation,
+                    value_iteration)
+from paper_2110_02901_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------- helpers
+
+def dense_random(n, m, seed, alpha=1.0, gamma=0.9):
+    P, c = inputs.dense_mdp(n, m, alpha, seed, dtype=np.float64)
+    return DenseMDP(P, c.astype(np.float64), gamma)
+
+
+def csr_random(n, m, k, seed, gamma=0.9, band=None):
+    rp, col, val, c = inputs.csr_mdp(n, m, k, 1.0, seed, band=band, val_dtype=np.float64)
+    return CsrMDP(rp, col, val, c.astype(np.float64), gamma)
+
+
+def csr_to_dense(mdp):
+    n, m = mdp.n, mdp.m
+    P = np.zeros((n * m, n))
+    for r in range(n * m):
+        for e in range(mdp.row_ptr[r], mdp.row_ptr[r + 1]):
+            P[r, mdp.col[e]] += mdp.val[e]
+    return DenseMDP(P.reshape(n, m, n), mdp.c, mdp.gamma)
+
+
+def textbook_T(P, c, gamma, V):
+    """Bellman operator, eq. (7), vectorised."""
+    return np.min(c + gamma * np.einsum("san,n->sa", P, V), axis=1)
+
+
+def textbook_F(P, c, gamma, V, order):
+    """Gauss-Seidel operator, Sec. II-D: one state at a time, in place."""
+    V = V.copy()
+    for s in order:
+        V[s] = min(c[s, a] + gamma * sum(P[s, a, j] * V[j] for j in range(len(V)))
+                   for a in range(c.shape[1]))
+    return V
+
+
+def policy_sweep_closed_form(P, c, gamma, V, b, order, mu):
+    """One sweep of B_{mu,b} as a linear system.  With pos(s) the position
+    of s in the order, state i reads the new value of j exactly when
+    pos(j) < b*floor(pos(i)/b) (eq. (10)).  Writing L for the part of P_mu
+    on those pairs: (I - gamma L) V' = c_mu + gamma (P_mu - L) V, and in
+    processing order I - gamma L is lower triangular."""
+    n = len(V)
+    Pm = P[np.arange(n), mu]
+    cm = c[np.arange(n), mu]
+    pos = np.empty(n, dtype=np.int64)
+    pos[order] = np.arange(n)
+    earlier = pos[None, :] < (b * (pos // b))[:, None]
+    L = np.where(earlier, Pm, 0.0)
+    rhs = cm + gamma * (Pm - L) @ V
+    A = np.eye(n) - gamma * L
+    Ao = A[np.ix_(order, order)]
+    assert np.allclose(Ao, np.tril(Ao))
+    x = scipy.linalg.solve_triangular(Ao, rhs[order], lower=True)
+    out = np.empty(n)
+    out[order] = x
+    return out
+
+
+def _frac(s):
+    return float(Fraction(s))
+
+
+def _hand():
+    ex = {}
+    with open(os.path.join(GOLDEN, "hand_examples.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                w = line.split()
+                ex[(w[0], w[1])] = np.array([_frac(x) for x in w[2:]])
+    return ex
+
+
+# ------------------------------------------------------- hand-worked pins
+
+def test_hand_example_A():
+    ex = _hand()
+    P = np.zeros((3, 1, 3))
+    P[0, 0, 2] = P[1, 0, 0] = P[2, 0, 1] = 1.0
+    mdp = DenseMDP(P, np.array([[1.0], [2.0], [3.0]]), 0.5)
+    order = np.array([0, 1, 2])
+    for b in (3, 1, 2):
+        V, arg, dv = mb_sweep(mdp, np.zeros(3), b, order)
+        assert np.array_equal(V, ex[("A", "b=%d" % b)])
+        assert dv == np.max(np.abs(V))
+    assert np.allclose(policy_value(mdp, [0, 0, 0]), ex[("A", "jstar")], atol=1e-14)
+    J, _ = brute_force_optimum(mdp)
+    assert np.allclose(J, ex[("A", "jstar")], atol=1e-14)
+
+
+def test_hand_example_B():
+    ex = _hand()
+    P = np.zeros((2, 2, 2))
+    P[0, 0, 0] = P[0, 1, 1] = P[1, 0, 0] = P[1, 1, 1] = 1.0
+    c = np.array([[1.0, 1.5], [2.0, 4.0]])
+    mdp = DenseMDP(P, c, 0.5)
+    order = np.array([1, 0])
+    V2, a2, _ = mb_sweep(mdp, np.zeros(2), 2, order)
+    V1, a1, _ = mb_sweep(mdp, np.zeros(2), 1, order)
+    assert np.array_equal(V2, ex[("B", "b=2")]) and np.array_equal(a2, [0, 0])
+    assert np.array_equal(V1, ex[("B", "b=1")]) and np.array_equal(a1, [0, 0])
+    V1b, _, _ = mb_sweep(mdp, V1, 1, order)
+    assert np.array_equal(V1b, ex[("B", "b=1,sweep2")])
+    J, opt = brute_force_optimum(mdp)
+    assert np.allclose(J, ex[("B", "jstar")], atol=1e-14)
+    assert [list(p) for p in opt] == [[0, 0]]
+
+
+# ---------------------------------------------- special cases b = n, b = 1
+
+@pytest.mark.parametrize("storage", ["dense", "csr"])
+def test_full_batch_is_bellman_operator(storage):
+    mdp = dense_random(40, 5, 11) if storage == "dense" else csr_random(40, 5, 6, 12)
+    D = mdp if storage == "dense" else csr_to_dense(mdp)
+    V = inputs.values(40, 3, 0, 5, dtype=np.float64)
+    expect = textbook_T(D.P, D.c, D.gamma, V)
+    for seed in (0, 1):
+        got, arg, _ = mb_sweep(mdp, V, 40, sweep_permutation(40, seed, 0))
+        assert np.allclose(got, expect, rtol=1e-13, atol=0)
+        Q = D.c + D.gamma * np.einsum("san,n->sa", D.P, V)
+        assert np.array_equal(arg, np.argmin(Q, axis=1))
+
+
+@pytest.mark.parametrize("storage", ["dense", "csr"])
+def test_unit_batch_is_gauss_seidel(storage):
+    mdp = dense_random(30, 4, 21) if storage == "dense" else csr_random(30, 4, 5, 22)
+    D = mdp if storage == "dense" else csr_to_dense(mdp)
+    V = inputs.values(30, 4, 0, 5, dtype=np.float64)
+    order = sweep_permutation(30, 5, 2)
+    expect = textbook_F(D.P, D.c, D.gamma, V, order)
+    got, _, _ = mb_sweep(mdp, V, 1, order)
+    assert np.allclose(got, expect, rtol=1e-13, atol=0)
+    # ascending order reproduces the paper's F exactly as printed
+    got_asc, _, _ = mb_sweep(mdp, V, 1, np.arange(30))
+    assert np.allclose(got_asc, textbook_F(D.P, D.c, D.gamma, V, range(30)), rtol=1e-13)
+
+
+def test_dense_and_csr_storage_agree():
+    mdp = csr_random(50, 3, 7, 31)
+    D = csr_to_dense(mdp)
+    V = inputs.values(50, 5, -2, 2, dtype=np.float64)
+    order = sweep_permutation(50, 1, 1)
+    for b in (1, 7, 50):
+        a, _, _ = mb_sweep(mdp, V, b, order)
+        d, _, _ = mb_sweep(D, V, b, order)
+        assert np.allclose(a, d, rtol=1e-13, atol=1e-14)
+
+
+# ------------------------------------------------------ closed-form pins
+
+@pytest.mark.parametrize("b", [1, 3, 8, 13, 37, 64])
+def test_policy_sweep_matches_closed_form(b):
+    n, m = 64, 4
+    mdp = dense_random(n, m, 41, gamma=0.95)
+    V = inputs.values(n, 6, 0, 10, dtype=np.float64)
+    mu = inputs.policy(n, m, 7).astype(np.int64)
+    order = sweep_permutation(n, 8, b)
+    got, arg, _ = mb_sweep(mdp, V, b, order, policy=mu)
+    expect = policy_sweep_closed_form(mdp.P, mdp.c, mdp.gamma, V, b, order, mu)
+    assert np.allclose(got, expect, rtol=1e-12, atol=1e-12)
+    assert np.array_equal(arg, mu)
+
+
+@pytest.mark.parametrize("b", [1, 5, 16, 50])
+def test_min_sweep_is_policy_sweep_of_its_argmin(b):
+    """B_b V equals B_{mu,b} V for mu = the returned argmin, and that argmin
+    minimises each state's bracket given what the state read."""
+    n, m = 50, 6
+    mdp = dense_random(n, m, 51, gamma=0.9)
+    V = inputs.values(n, 9, 0, 4, dtype=np.float64)
+    order = sweep_permutation(n, 10, 0)
+    got, arg, _ = mb_sweep(mdp, V, b, order)
+    expect = policy_sweep_closed_form(mdp.P, mdp.c, mdp.gamma, V, b, order, arg)
+    assert np.allclose(got, expect, rtol=1e-12, atol=1e-12)
+    pos = np.empty(n, dtype=np.int64)
+    pos[order] = np.arange(n)
+    for s in range(n):
+        seen = np.where(pos < b * (pos[s] // b), got, V)
+        Q = mdp.c[s] + mdp.gamma * mdp.P[s] @ seen
+        assert Q[arg[s]] == pytest.approx(Q.min(), rel=1e-13)
+        assert arg[s] == np.argmin(Q)
+
+
+def test_policy_value_solves_bellman_equation_and_is_limit():
+    n, m = 40, 3
+    mdp = dense_random(n, m, 61, gamma=0.8)
+    mu = inputs.policy(n, m, 2).astype(np.int64)
+    J = policy_value(mdp, mu)
+    Pm = mdp.P[np.arange(n), mu]
+    assert np.allclose(J, mdp.c[np.arange(n), mu] + mdp.gamma * Pm @ J, atol=1e-12)
+    # eq. (8): T_mu^k J -> J_mu (Jacobi iteration, no linear solve)
+    V = np.zeros(n)
+    for _ in range(200):
+        V = mdp.c[np.arange(n), mu] + mdp.gamma * Pm @ V
+    assert np.allclose(V, J, atol=1e-12)
+    csr = csr_random(30, 3, 4, 62, gamma=0.8)
+    mu = inputs.policy(30, 3, 3).astype(np.int64)
+    assert np.allclose(policy_value(csr, mu), policy_value(csr_to_dense(csr), mu), atol=1e-12)
+    assert np.allclose(policy_value(csr, mu, iterative_tol=1e-13),
+                       policy_value(csr, mu), atol=1e-10)
+
+
+# ------------------------------------------------- J* and the drivers
+
+@pytest.mark.parametrize("n,m,seed", [(4, 3, 71), (5, 2, 72), (6, 2, 73), (3, 3, 74)])
+def test_solvers_reach_brute_force_optimum(n, m, seed):
+    mdp = dense_random(n, m, seed, gamma=0.9)
+    J, optimal = brute_force_optimum(mdp)
+    Vpi, mupi, _ = policy_iteration(mdp)
+    assert np.allclose(Vpi, J, atol=1e-12)
+    assert any(np.array_equal(mupi, p) for p in optimal)
+    for b in (1, 2, n):
+        V, pol, st = value_iteration(mdp, b, seed=5, tol_dv=1e-13, max_sweeps=2000)
+        assert st.converged
+        assert np.max(np.abs(V - J)) < 1e-11
+        assert any(np.array_equal(pol, p) for p in optimal)
+        Vm, mum, stm = modified_policy_iteration(mdp, K=3, b=b, seed=6, tol_dv=1e-13)
+        assert stm.converged and np.max(np.abs(Vm - J)) < 1e-11
+        assert any(np.array_equal(mum, p) for p in optimal)
+
+
+def test_inadmissible_actions_are_never_chosen():
+    n, m = 5, 3
+    mdp = dense_random(n, m, 81)
+    mdp.c = inputs.inadmissible(mdp.c, 0.4, 3).astype(np.float64)
+    J, optimal = brute_force_optimum(mdp)
+    V, pol, st = value_iteration(mdp, 2, seed=1, tol_dv=1e-13, max_sweeps=5000)
+    assert np.max(np.abs(V - J)) < 1e-11
+    assert np.all(np.isfinite(mdp.c[np.arange(n), pol]))
+    Vpi, mupi, _ = policy_iteration(mdp)
+    assert np.allclose(Vpi, J, atol=1e-12)
+
+
+def test_value_iteration_reference_stop_and_resume():
+    mdp = dense_random(30, 3, 91, gamma=0.9)
+    Vstar, _, _ = policy_iteration(mdp)
+    V, _, st = value_iteration(mdp, 7, seed=3, tol_dv=-1, V_ref=Vstar, eps=1e-6)
+    assert st.converged and st.final_err_ref <= 1e-6
+    # the previous sweep was not yet within eps: first crossing
+    Vp, _, stp = value_iteration(mdp, 7, seed=3, tol_dv=-1, max_sweeps=st.sweeps - 1)
+    assert np.max(np.abs(Vp - Vstar)) > 1e-6
+    # resuming at sweep t0 reproduces the uninterrupted run bit for bit
+    full, _, _ = value_iteration(mdp, 7, seed=3, tol_dv=-1, max_sweeps=20)
+    part, _, _ = value_iteration(mdp, 7, seed=3, tol_dv=-1, max_sweeps=12)
+    rest, _, _ = value_iteration(mdp, 7, seed=3, V0=part, tol_dv=-1, max_sweeps=8,
+                                 first_sweep=12)
+    assert np.array_equal(full, rest)
+
+
+def test_mpi_outer_structure():
+    """With K = 1 and b = n, MB-MPI alternates one T_mu step with a greedy
+    step; the first evaluation step from V0 = 0 with mu0 = argmin c gives
+    exactly T(0) = min_a c."""
+    mdp = dense_random(20, 4, 95, gamma=0.9)
+    V, mu, st = modified_policy_iteration(mdp, K=1, b=20, seed=0, max_outer=1, tol_dv=-1)
+    assert np.allclose(V, mdp.c.min(axis=1), atol=0)
+    assert st.outer_iters == 1 and st.sweeps == 1
+
+
+# --------------------------------------------------- lemmas, Sec. III-B
+
+def _iterate(mdp, V, b, seed, k, policy=None):
+    for t in range(k):
+        V, _, _ = mb_sweep(mdp, V, b, sweep_permutation(mdp.n, seed, t), policy=policy)
+    return V
+
+
+@pytest.mark.parametrize("b", [1, 6, 25, 60])
+def test_monotonicity(b):
+    n, m = 60, 4
+    mdp = dense_random(n, m, 101)
+    V = inputs.values(n, 11, 0, 3, dtype=np.float64)
+    Vp = V + np.abs(inputs.values(n, 12, 0, 1, dtype=np.float64))
+    mu = inputs.policy(n, m, 13).astype(np.int64)
+    for k in (1, 2, 5):
+        assert np.all(_iterate(mdp, V, b, 4, k) <= _iterate(mdp, Vp, b, 4, k) + 1e-13)
+        assert np.all(_iterate(mdp, V, b, 4, k, mu) <= _iterate(mdp, Vp, b, 4, k, mu) + 1e-13)
+
+
+def test_hand_example_C_shift():
+    ex = _hand()
+    P = np.zeros((2, 1, 2))
+    P[0, 0, 1] = P[1, 0, 0] = 1.0
+    mdp = DenseMDP(P, np.ones((2, 1)), 0.5)
+    order = np.array([0, 1])
+    for b in (1, 2):
+        shifted = mb_sweep(mdp, np.ones(2), b, order)[0] - mb_sweep(mdp, np.zeros(2), b, order)[0]
+        assert np.array_equal(shifted, ex[("C", "b=%d,shift" % b)])
+
+
+@pytest.mark.parametrize("b", [1, 9, 60])
+def test_shift_invariance(b):
+    """Shift lemma of Sec. III-B.1.  For b = n (the Bellman operator) the
+    stated equality B^k(V + r e) = B^k V + gamma^k r e holds.  For b < n its
+    proof does not go through (states that read already-updated values see
+    the shift gamma*r, not r; see hand example C), and what holds is the
+    two-sided bound B^k V <= B^k(V + r e) <= B^k V + gamma^k r e for r >= 0,
+    which is all the contraction proof needs."""
+    n, m = 60, 4
+    mdp = dense_random(n, m, 111, gamma=0.93)
+    V = inputs.values(n, 14, 0, 3, dtype=np.float64)
+    for r in (2.5, 7.0):
+        for k in (1, 3):
+            lhs = _iterate(mdp, V + r, b, 5, k)
+            base = _iterate(mdp, V, b, 5, k)
+            if b == n:
+                assert np.allclose(lhs, base + mdp.gamma**k * r, rtol=0, atol=1e-12)
+            else:
+                assert np.all(base <= lhs + 1e-12)
+                assert np.all(lhs <= base + mdp.gamma**k * r + 1e-12)
+                assert np.max(base + mdp.gamma**k * r - lhs) > 1e-3  # equality fails
+            lhs_neg = _iterate(mdp, V - r, b, 5, k)
+            assert np.all(base - mdp.gamma**k * r <= lhs_neg + 1e-12)
+            assert np.all(lhs_neg <= base + 1e-12)
+
+
+@pytest.mark.parametrize("b", [1, 9, 60])
+def test_contraction(b):
+    n, m = 60, 4
+    mdp = dense_random(n, m, 121, gamma=0.9)
+    V = inputs.values(n, 15, 0, 3, dtype=np.float64)
+    W = inputs.values(n, 16, -5, 8, dtype=np.float64)
+    d0 = np.max(np.abs(V - W))
+    for k in (1, 2, 4):
+        dk = np.max(np.abs(_iterate(mdp, V, b, 6, k) - _iterate(mdp, W, b, 6, k)))
+        assert dk <= mdp.gamma**k * d0 + 1e-12
+
+
+def test_fixed_points_for_every_batch_size_and_order():
+    n, m = 48, 5
+    mdp = dense_random(n, m, 131, gamma=0.95)
+    Vstar, mustar, _ = policy_iteration(mdp)
+    mu = inputs.policy(n, m, 17).astype(np.int64)
+    Jmu = policy_value(mdp, mu)
+    for b in (1, 5, 16, 47, 48):
+        for seed in (0, 1):
+            order = sweep_permutation(n, seed, b)
+            assert np.max(np.abs(mb_sweep(mdp, Vstar, b, order)[0] - Vstar)) < 1e-12
+            assert np.max(np.abs(mb_sweep(mdp, Jmu, b, order, policy=mu)[0] - Jmu)) < 1e-12
+
+
+@pytest.mark.parametrize("storage", ["dense", "csr"])
+def test_batch_size_ordering(storage):
+    """Theorem and Corollary of Sec. III-B.2 with V0 = 0 and c >= 0 (so
+    V0 <= T V0 <= J*): T^k V0 <= B_b^k V0 <= B_b'^k V0 <= F^k V0 <= J* for
+    b' dividing b (the batches of b' refine those of b, which the proof
+    needs for M_b(i) to be contained in M_b'(i)), all with the same
+    sequence of orders."""
+    n = 64
+    mdp = dense_random(n, 4, 141, alpha=0.5, gamma=0.95) if storage == "dense" \
+        else csr_random(n, 4, 8, 142, gamma=0.95)
+    Vstar, _, _ = policy_iteration(mdp)
+    V = {b: np.zeros(n) for b in (64, 32, 8, 4, 1)}
+    for t in range(25):
+        order = sweep_permutation(n, 7, t)
+        for b in V:
+            V[b] = mb_sweep(mdp, V[b], b, order)[0]
+        chain = [V[64], V[32], V[8], V[4], V[1], Vstar]
+        for lo, hi in zip(chain, chain[1:]):
+            assert np.all(lo <= hi + 1e-12)
+    assert np.max(V[1] - V[64]) > 1e-3  # the ordering is strict somewhere
+
+
+# ------------------------------------------------ re-centring (shift)
+
+def test_row_sums():
+    mdp = csr_random(30, 3, 5, 151)
+    assert np.allclose(row_sums(mdp), csr_to_dense(mdp).P.sum(axis=2), atol=1e-15)
+    P32 = inputs.dense_dirichlet(20, 3, 0.1, 5, dtype=np.float32)
+    d = DenseMDP(P32, np.zeros((20, 3)), 0.9)
+    assert np.array_equal(row_sums(d), P32.astype(np.float64).sum(axis=2))
+
+
+@pytest.mark.parametrize("b", [1, 7, 40])
+def test_shifted_costs_give_shifted_iterates(b):
+    """Iterating W = V - r e with c' equals iterating V with c, minus r, for
+    non-stochastic rows too (FP32-rounded P), because c' uses the row sums."""
+    n, m = 40, 4
+    P32 = inputs.dense_dirichlet(n, m, 0.3, 161, dtype=np.float32)
+    c = inputs.costs(n, m, 161).astype(np.float64)
+    mdp = DenseMDP(P32, c, 0.99)
+    V = inputs.values(n, 18, 5, 6, dtype=np.float64)
+    for r in (5.5, -3.0):
+        sh = DenseMDP(P32, shifted_costs(mdp, r), 0.99)
+        for t in range(3):
+            order = sweep_permutation(n, 9, t)
+            a, arg_a, _ = mb_sweep(mdp, V, b, order)
+            w, arg_w, _ = mb_sweep(sh, V - r, b, order)
+            assert np.allclose(w + r, a, rtol=0, atol=1e-12)
+            assert np.array_equal(arg_a, arg_w)
+
+
+def test_q_values_policy_form_matches_full_form():
+    mdp = csr_random(25, 4, 6, 171)
+    V = inputs.values(25, 19, dtype=np.float64)
+    mu = inputs.policy(25, 4, 20).astype(np.int64)
+    states = np.arange(25)
+    full = q_values(mdp, states, V)
+    assert np.allclose(q_values(mdp, states, V, actions=mu), full[states, mu], rtol=1e-15)
+    TV, g = greedy(mdp, V)
+    assert np.array_equal(TV, full.min(axis=1)) and np.array_equal(g, full.argmin(axis=1))
+
+
+def test_oracle_header_declares_test_infrastructure():
+    assert "TEST INFRASTRUCTURE ONLY" in oracle.__doc__
