@@ -1,0 +1,199 @@
+/*
+ * mbdp.h -- C-ABI of the MI355X (gfx950) randomized mini-batch Bellman
+ * operator library, libmbdp.so.
+ *
+ * Paper: M. Gargiani, A. Martinelli, M. Ruts Martinez, J. Lygeros, "Parallel
+ * and Flexible Dynamic Programming via the Randomized Mini-Batch Operator",
+ * arXiv 2110.02901.  Section and equation numbers below are the paper's.
+ *
+ * Problem (Sec. II-A): a finite MDP with n states, m actions per state,
+ * transition probabilities P(s, a, s'), stage costs c(s, a) and a discount
+ * gamma in (0, 1); the goal is the minimal discounted cost J* (eq. (2)).
+ * A cost of +inf marks an action that is not admissible in its state (the
+ * paper's U(i)); every state needs at least one finite-cost action.  The
+ * paper's batch size "m" is called b here; its "alpha" is gamma and its cost
+ * vector J is V.
+ *
+ * Conventions for every entry point:
+ *  - All arrays named as device arrays live in HBM of the current HIP device
+ *    and are BORROWED: the caller allocates them, keeps them alive and does
+ *    not modify them while a call that uses them may run.  The library
+ *    allocates no device memory; scratch space comes from a caller-provided
+ *    workspace of mdp_workspace_bytes() bytes (256-byte aligned).
+ *  - Transition row r = s*m + a.  Dense P is [n][m][n] FP32, row-major, so
+ *    the m rows of a state are contiguous.  Costs c are [n][m] FP32.  V is
+ *    FP32[n].  Policies are int32[n] with entries in [0, m).
+ *  - Arguments are checked before any device work; a bad argument returns
+ *    MBDP_ERR_INVALID_ARG and touches nothing.  No entry point throws or
+ *    exits.  mbdp_last_error() gives a message for the last failure on the
+ *    calling thread.
+ *  - A handle and a workspace are used by one stream at a time; calls that
+ *    share a workspace must not overlap.
+ *  - Device work runs on the given stream.  mb_sweep and mbdp_permutation
+ *    are asynchronous; mdp_create_csr, mdp_validate, vi_solve and mpi_solve
+ *    synchronise the stream before returning.
+ */
+#ifndef MBDP_H
+#define MBDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mbdp_mdp* mbdp_mdp_t; /* opaque handle */
+
+typedef enum {
+  MBDP_OK = 0,
+  MBDP_ERR_INVALID_ARG = 1,   /* bad size, pointer, batch size, gamma, K ... */
+  MBDP_ERR_UNSUPPORTED = 2,   /* valid request the library cannot serve */
+  MBDP_ERR_WORKSPACE = 3,     /* workspace missing, too small or misaligned */
+  MBDP_ERR_HIP = 4,           /* a HIP runtime call failed */
+  MBDP_ERR_NOT_CONVERGED = 5, /* soft: iteration limit reached, V and stats valid */
+  MBDP_ERR_VALIDATION = 6,    /* mdp_validate found an invalid MDP */
+  MBDP_ERR_DEVICE = 7         /* device-side error (bad explicit order, barrier timeout) */
+} mbdp_status;
+
+/* Statistics of a solve (vi_solve, mpi_solve). */
+typedef struct {
+  int64_t sweeps;              /* sweeps of B_b or B_{mu,b} applied */
+  int64_t outer_iters;         /* MPI policy-improvement steps (0 for VI) */
+  int64_t policy_changes_last; /* states whose action changed in the last improvement (-1: none) */
+  int64_t recentrings;         /* number of re-centring steps */
+  double final_dv_inf;         /* VI: max|V_{t+1} - V_t| of the last sweep;
+                                  MPI: Bellman residual max|TV - V| of the last improvement */
+  double final_err_ref;        /* max|V - V_ref| after the last sweep (NaN without V_ref) */
+  double shift;                /* final re-centring offset r (V = W + r) */
+  int32_t converged;           /* 1 if a stopping rule fired before the limit */
+  int32_t reserved;
+} mbdp_stats;
+
+/* Result of mdp_validate. */
+typedef struct {
+  int64_t bad_probability;     /* entries < 0, NaN or inf in P */
+  int64_t bad_row_sum;         /* rows whose FP64 sum differs from 1 by more than the tolerance */
+  int64_t empty_rows;          /* CSR rows without entries */
+  int64_t bad_column;          /* CSR column outside [0, n) */
+  int64_t bad_row_ptr;         /* CSR row_ptr not non-decreasing / inconsistent with nnz */
+  int64_t bad_cost;            /* costs NaN or -inf */
+  int64_t no_admissible_action;/* states whose costs are all +inf */
+  double max_row_sum_dev;      /* max |sum_s' P(s,a,s') - 1| over rows */
+} mbdp_validation;
+
+/* Tuning knobs of a handle (all fields 0 = library default). */
+typedef struct {
+  int32_t blocks_per_cu;       /* persistent workgroups per compute unit */
+  int32_t threads_per_block;   /* 256, 512 or 1024 */
+  int32_t recentre_every;      /* solvers: sweeps between re-centrings; -1 disables */
+  int32_t reserved;
+} mbdp_tuning;
+
+/* Dense MDP (P as in Sec. II-A, stored [n][m][n]).  Records the pointers;
+ * does no device work.  P and c are device arrays. */
+mbdp_status mdp_create_dense(int64_t n, int32_t m, const float* P, const float* c,
+                             double gamma, mbdp_mdp_t* out);
+
+/* Sparse MDP: CSR over the n*m transition rows.  row_ptr int64[n*m + 1]
+ * (row_ptr[0] = 0, row_ptr[n*m] = nnz), col int32[nnz] in [0, n), val
+ * FP32[nnz]; a repeated column contributes once per entry.  All are device
+ * arrays.  Inspects row_ptr on the device (synchronising `stream`) to detect
+ * a constant row length k, which selects a faster kernel. */
+mbdp_status mdp_create_csr(int64_t n, int32_t m, const int64_t* row_ptr, const int32_t* col,
+                           const float* val, int64_t nnz, const float* c, double gamma,
+                           hipStream_t stream, mbdp_mdp_t* out);
+
+/* Releases the handle (not the borrowed arrays).  NULL is a no-op. */
+mbdp_status mdp_destroy(mbdp_mdp_t h);
+
+/* Replaces the handle's tuning knobs. */
+mbdp_status mdp_set_tuning(mbdp_mdp_t h, const mbdp_tuning* t);
+
+/* Workspace bytes that mb_sweep, vi_solve, mpi_solve and mdp_validate need
+ * for this handle with batch size b (0 on a bad handle or batch size). */
+size_t mdp_workspace_bytes(mbdp_mdp_t h, int64_t b);
+
+/* Optional input checks: P entries in [0, inf), FP64 row sums within
+ * row_sum_tol of 1, CSR structure, costs not NaN/-inf and at least one
+ * finite cost per state.  Fills *report (may be NULL) and returns MBDP_OK
+ * or MBDP_ERR_VALIDATION.  Synchronises `stream`. */
+mbdp_status mdp_validate(mbdp_mdp_t h, double row_sum_tol, void* workspace, size_t ws_bytes,
+                         hipStream_t stream, mbdp_validation* report);
+
+/* The sweep order sigma_t of the states (Sec. III-A processes states in a
+ * random order, re-drawn every sweep; Sec. IV-A shuffles before every
+ * operator evaluation): out[p] = state processed at position p of sweep
+ * `sweep_index` under `seed`, for p in [0, n).  out is a device int32[n].
+ * The order is a 4-round Feistel network on [0, 4^h) (h the smallest h >= 1
+ * with 4^h >= n) whose round function j maps R to word 0 of
+ * Philox-4x32-10(counter = (R, j, t_lo, t_hi), key = (seed_lo, seed_hi))
+ * masked to h bits, restricted to [0, n) by cycle walking. */
+mbdp_status mbdp_permutation(int64_t n, uint64_t seed, uint64_t sweep_index, int32_t* out,
+                             hipStream_t stream);
+
+/* One sweep of the mini-batch operator, eqs. (10)-(12).  The states are
+ * processed in the order sigma_t (t = sweep_index), or in the explicit order
+ * perm (device int32[n], a permutation of [0, n)) when perm != NULL, cut into
+ * consecutive batches of b (the last batch may be shorter).  Each state of a
+ * batch reads the new values of earlier batches and the old values of its
+ * own and later batches; the batch is committed after all its reads.
+ *   policy == NULL: B_b,      V(s) <- min_a [c(s,a) + gamma sum_s' P(s,a,s') V(s')]
+ *   policy != NULL: B_{mu,b}, V(s) <- c(s,mu(s)) + gamma sum_s' P(s,mu(s),s') V(s')
+ * 1 <= b <= n; b = n is the Bellman operator T (eq. (7)) and b = 1 the
+ * Gauss-Seidel operator F (Sec. II-D).  V (device FP32[n]) is updated in
+ * place.  argmin_out (device int32[n], may be NULL) receives the lowest
+ * minimising action (or mu(s)).  dv_out (device float[1], may be NULL)
+ * receives max_s |V_new(s) - V_old(s)|.  Dot products accumulate in FP32;
+ * the cost is added and the minimum taken in FP64, then rounded to FP32.
+ * Asynchronous; device-side errors (an out-of-range perm entry) are
+ * reported by mbdp_sync_status. */
+mbdp_status mb_sweep(mbdp_mdp_t h, float* V, const int32_t* policy, int64_t b, uint64_t seed,
+                     uint64_t sweep_index, const int32_t* perm, int32_t* argmin_out,
+                     float* dv_out, void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Synchronises `stream` and returns the device-side status recorded in
+ * `workspace` by the last mb_sweep/vi_solve/mpi_solve that used it. */
+mbdp_status mbdp_sync_status(void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* MB-VI (Sec. III-B): from the caller's V (the paper starts at 0, Sec.
+ * IV-A), apply sweeps t = first_sweep, first_sweep + 1, ... of B_b with
+ * order sigma_t until max|V_{t+1} - V_t| <= tol_dv (tol_dv < 0 disables),
+ * or -- when V_ref (device FP64[n]) is given -- max|V_{t+1} - V_ref| <= eps,
+ * or max_sweeps sweeps.  All sweeps run in one persistent kernel launch
+ * with a device-wide barrier between batches.  The iterate is kept as
+ * W = V - r with costs c - r + gamma*r*rowsum(P) (exact in real arithmetic)
+ * and r re-centred every few sweeps, so FP32 resolves V to ~ulp(max|W|).
+ * On return V holds the last iterate and, if policy_out (device int32[n])
+ * is given, the greedy policy at V (lowest index on ties).  stats may be
+ * NULL.  Returns MBDP_ERR_NOT_CONVERGED when the limit was reached. */
+mbdp_status vi_solve(mbdp_mdp_t h, float* V, int32_t* policy_out, int64_t b, uint64_t seed,
+                     uint64_t first_sweep, double tol_dv, double eps, const double* V_ref,
+                     int64_t max_sweeps, void* workspace, size_t ws_bytes, hipStream_t stream,
+                     mbdp_stats* stats);
+
+/* MB-MPI: Algorithm 1 with its K policy-evaluation steps done by B_{mu,b}
+ * (warm start from the current V).  policy (device int32[n]) is the initial
+ * policy when policy_is_init != 0; otherwise the initial policy is the
+ * greedy policy at the caller's V.  Each outer iteration runs K sweeps of
+ * B_{mu,b} (orders sigma_t, t counting evaluation sweeps from first_sweep)
+ * and then the improvement step over all states (V fixed).  Stops when an
+ * improvement changes no action and the Bellman residual max|TV - V| is
+ * <= tol_dv, or -- with V_ref -- after the first evaluation sweep with
+ * max|V - V_ref| <= eps, or after max_outer outer iterations.  On return V
+ * and policy hold the last iterate. */
+mbdp_status mpi_solve(mbdp_mdp_t h, float* V, int32_t* policy, int32_t policy_is_init, int32_t K,
+                      int64_t b, uint64_t seed, uint64_t first_sweep, double tol_dv, double eps,
+                      const double* V_ref, int64_t max_outer, void* workspace, size_t ws_bytes,
+                      hipStream_t stream, mbdp_stats* stats);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* mbdp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MBDP_H */

@@ -1,0 +1,288 @@
+"""Python binding of libmbdp.so: the C-ABI of include/mbdp.h, by the same names.
+
+Argument marshalling only: every step runs in the HIP library.  Tensors are
+torch tensors on the current HIP device; their data pointers are passed
+through, and the current torch stream is used unless one is given.  A
+missing library raises ``MbdpLibraryMissing``; a failing call raises
+``MbdpError`` with the library's status and message (a not-converged solve
+returns its statistics with ``converged`` False instead).
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmbdp.so")
+
+MBDP_OK = 0
+MBDP_ERR_INVALID_ARG = 1
+MBDP_ERR_UNSUPPORTED = 2
+MBDP_ERR_WORKSPACE = 3
+MBDP_ERR_HIP = 4
+MBDP_ERR_NOT_CONVERGED = 5
+MBDP_ERR_VALIDATION = 6
+MBDP_ERR_DEVICE = 7
+
+STATUS_NAMES = {
+    0: "MBDP_OK", 1: "MBDP_ERR_INVALID_ARG", 2: "MBDP_ERR_UNSUPPORTED",
+    3: "MBDP_ERR_WORKSPACE", 4: "MBDP_ERR_HIP", 5: "MBDP_ERR_NOT_CONVERGED",
+    6: "MBDP_ERR_VALIDATION", 7: "MBDP_ERR_DEVICE",
+}
+
+# Every symbol include/mbdp.h declares.
+EXPORTS = [
+    "mdp_create_dense", "mdp_create_csr", "mdp_destroy", "mdp_set_tuning",
+    "mdp_workspace_bytes", "mdp_validate", "mbdp_permutation", "mb_sweep",
+    "mbdp_sync_status", "vi_solve", "mpi_solve", "mbdp_last_error",
+]
+
+
+class MbdpLibraryMissing(RuntimeError):
+    pass
+
+
+class MbdpError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("outer_iters", ctypes.c_int64),
+                ("policy_changes_last", ctypes.c_int64), ("recentrings", ctypes.c_int64),
+                ("final_dv_inf", ctypes.c_double), ("final_err_ref", ctypes.c_double),
+                ("shift", ctypes.c_double), ("converged", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class Validation(ctypes.Structure):
+    _fields_ = [("bad_probability", ctypes.c_int64), ("bad_row_sum", ctypes.c_int64),
+                ("empty_rows", ctypes.c_int64), ("bad_column", ctypes.c_int64),
+                ("bad_row_ptr", ctypes.c_int64), ("bad_cost", ctypes.c_int64),
+                ("no_admissible_action", ctypes.c_int64), ("max_row_sum_dev", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("threads_per_block", ctypes.c_int32),
+                ("recentre_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_U64 = ctypes.c_uint64
+_I32 = ctypes.c_int32
+_D = ctypes.c_double
+_SIGS = {
+    "mdp_create_dense": (_I32, [_I64, _I32, _P, _P, _D, ctypes.POINTER(_P)]),
+    "mdp_create_csr": (_I32, [_I64, _I32, _P, _P, _P, _I64, _P, _D, _P, ctypes.POINTER(_P)]),
+    "mdp_destroy": (_I32, [_P]),
+    "mdp_set_tuning": (_I32, [_P, ctypes.POINTER(Tuning)]),
+    "mdp_workspace_bytes": (ctypes.c_size_t, [_P, _I64]),
+    "mdp_validate": (_I32, [_P, _D, _P, ctypes.c_size_t, _P, ctypes.POINTER(Validation)]),
+    "mbdp_permutation": (_I32, [_I64, _U64, _U64, _P, _P]),
+    "mb_sweep": (_I32, [_P, _P, _P, _I64, _U64, _U64, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "mbdp_sync_status": (_I32, [_P, ctypes.c_size_t, _P]),
+    "vi_solve": (_I32, [_P, _P, _P, _I64, _U64, _U64, _D, _D, _P, _I64, _P, ctypes.c_size_t,
+                        _P, ctypes.POINTER(Stats)]),
+    "mpi_solve": (_I32, [_P, _P, _P, _I32, _I32, _I64, _U64, _U64, _D, _D, _P, _I64, _P,
+                         ctypes.c_size_t, _P, ctypes.POINTER(Stats)]),
+    "mbdp_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libmbdp.so (loaded once)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise MbdpLibraryMissing(
+                "libmbdp.so is not built (%s); run __graft_entry__.build() or "
+                "python -m paper_2110_02901_amd.build" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error():
+    return lib().mbdp_last_error().decode()
+
+
+def _check(status):
+    if status != MBDP_OK:
+        raise MbdpError(status, last_error())
+    return status
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _require(t, dtype, numel=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_cuda:
+        raise ValueError("%s must be on the GPU" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s must have %d elements, got %d" % (name, numel, t.numel()))
+
+
+class Handle:
+    """An mbdp_mdp_t plus references that keep its borrowed tensors alive."""
+
+    def __init__(self, ptr, n, m, keep):
+        self.ptr = ptr
+        self.n = n
+        self.m = m
+        self._keep = keep
+
+    def close(self):
+        if self.ptr:
+            lib().mdp_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mdp_create_dense(P, c, gamma):
+    import torch
+    n, m = c.shape
+    _require(P, torch.float32, n * m * n, "P")
+    _require(c, torch.float32, n * m, "c")
+    h = ctypes.c_void_p()
+    _check(lib().mdp_create_dense(n, m, _ptr(P), _ptr(c), float(gamma), ctypes.byref(h)))
+    return Handle(h, n, m, (P, c))
+
+
+def mdp_create_csr(row_ptr, col, val, c, gamma, stream=None):
+    import torch
+    n, m = c.shape
+    _require(row_ptr, torch.int64, n * m + 1, "row_ptr")
+    _require(col, torch.int32, None, "col")
+    _require(val, torch.float32, col.numel(), "val")
+    _require(c, torch.float32, n * m, "c")
+    h = ctypes.c_void_p()
+    _check(lib().mdp_create_csr(n, m, _ptr(row_ptr), _ptr(col), _ptr(val), col.numel(),
+                                _ptr(c), float(gamma), _stream(stream), ctypes.byref(h)))
+    return Handle(h, n, m, (row_ptr, col, val, c))
+
+
+def mdp_destroy(h):
+    h.close()
+
+
+def mdp_set_tuning(h, blocks_per_cu=0, threads_per_block=0, recentre_every=0):
+    t = Tuning(blocks_per_cu, threads_per_block, recentre_every, 0)
+    _check(lib().mdp_set_tuning(h.ptr, ctypes.byref(t)))
+
+
+def mdp_workspace_bytes(h, b):
+    return int(lib().mdp_workspace_bytes(h.ptr, int(b)))
+
+
+def workspace(h, b):
+    """A torch uint8 workspace tensor of the required size (256-byte aligned)."""
+    import torch
+    nbytes = mdp_workspace_bytes(h, b)
+    if nbytes == 0:
+        raise MbdpError(MBDP_ERR_INVALID_ARG, "bad handle or batch size %r" % (b,))
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
+def mdp_validate(h, row_sum_tol, ws, stream=None):
+    rep = Validation()
+    st = lib().mdp_validate(h.ptr, float(row_sum_tol), _ptr(ws), ws.numel(), _stream(stream),
+                            ctypes.byref(rep))
+    if st not in (MBDP_OK, MBDP_ERR_VALIDATION):
+        _check(st)
+    return st == MBDP_OK, rep.as_dict()
+
+
+def mbdp_permutation(n, seed, sweep_index, out, stream=None):
+    import torch
+    _require(out, torch.int32, n, "out")
+    _check(lib().mbdp_permutation(int(n), int(seed), int(sweep_index), _ptr(out), _stream(stream)))
+    return out
+
+
+def mb_sweep(h, V, b, seed, sweep_index, ws, policy=None, perm=None, argmin_out=None,
+             dv_out=None, stream=None):
+    import torch
+    _require(V, torch.float32, h.n, "V")
+    if policy is not None:
+        _require(policy, torch.int32, h.n, "policy")
+    if perm is not None:
+        _require(perm, torch.int32, h.n, "perm")
+    if argmin_out is not None:
+        _require(argmin_out, torch.int32, h.n, "argmin_out")
+    if dv_out is not None:
+        _require(dv_out, torch.float32, 1, "dv_out")
+    _check(lib().mb_sweep(h.ptr, _ptr(V), _ptr(policy), int(b), int(seed), int(sweep_index),
+                          _ptr(perm), _ptr(argmin_out), _ptr(dv_out), _ptr(ws), ws.numel(),
+                          _stream(stream)))
+
+
+def mbdp_sync_status(ws, stream=None):
+    _check(lib().mbdp_sync_status(_ptr(ws), ws.numel(), _stream(stream)))
+
+
+def vi_solve(h, V, b, seed, ws, first_sweep=0, tol_dv=-1.0, eps=0.0, V_ref=None,
+             max_sweeps=100000, policy_out=None, stream=None):
+    """Returns the statistics dict (``converged`` False when the limit was hit)."""
+    import torch
+    _require(V, torch.float32, h.n, "V")
+    if V_ref is not None:
+        _require(V_ref, torch.float64, h.n, "V_ref")
+    if policy_out is not None:
+        _require(policy_out, torch.int32, h.n, "policy_out")
+    st = Stats()
+    status = lib().vi_solve(h.ptr, _ptr(V), _ptr(policy_out), int(b), int(seed), int(first_sweep),
+                            float(tol_dv), float(eps), _ptr(V_ref), int(max_sweeps), _ptr(ws),
+                            ws.numel(), _stream(stream), ctypes.byref(st))
+    if status != MBDP_ERR_NOT_CONVERGED:
+        _check(status)
+    return st.as_dict()
+
+
+def mpi_solve(h, V, policy, K, b, seed, ws, policy_is_init=True, first_sweep=0, tol_dv=-1.0,
+              eps=0.0, V_ref=None, max_outer=10000, stream=None):
+    import torch
+    _require(V, torch.float32, h.n, "V")
+    _require(policy, torch.int32, h.n, "policy")
+    if V_ref is not None:
+        _require(V_ref, torch.float64, h.n, "V_ref")
+    st = Stats()
+    status = lib().mpi_solve(h.ptr, _ptr(V), _ptr(policy), int(bool(policy_is_init)), int(K),
+                             int(b), int(seed), int(first_sweep), float(tol_dv), float(eps),
+                             _ptr(V_ref), int(max_outer), _ptr(ws), ws.numel(), _stream(stream),
+                             ctypes.byref(st))
+    if status != MBDP_ERR_NOT_CONVERGED:
+        _check(status)
+    return st.as_dict()

@@ -1,0 +1,146 @@
+// Internal definitions shared by the HIP kernels and the host runtime of
+// libmbdp.so.  Not part of the public C-ABI (include/mbdp.h).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mbdp {
+
+enum Storage : int32_t { kDense = 0, kEll = 1, kCsr = 2 };
+enum Task : int32_t { kTaskSweep = 0, kTaskVI = 1, kTaskMPI = 2 };
+
+// Device-side error codes recorded in Control::error.
+enum DeviceError : uint32_t {
+  kDevOk = 0,
+  kDevBadPerm = 1,        // explicit order entry outside [0, n)
+  kDevBarrierTimeout = 2, // a grid barrier waited longer than the limit
+  kDevBadPolicy = 3,      // policy entry outside [0, m)
+};
+
+// Accumulators of one epoch (a sweep or an improvement pass).  Doubles are
+// kept as order-preserving 64-bit keys so that atomic max/min on unsigned
+// integers give the max/min of the values.
+enum Acc : int {
+  kAccDv = 0,      // max |W_new - W_old| (non-negative double bits)
+  kAccErr = 1,     // max |W_new + r - V_ref|
+  kAccWmax = 2,    // max W_new (ordered key)
+  kAccWmin = 3,    // min W_new (ordered key)
+  kAccChanges = 4, // policy changes (count)
+  kAccResid = 5,   // max |TW - W| (non-negative double bits)
+  kNumAcc = 6
+};
+
+struct alignas(256) Control {
+  unsigned long long bar_count;  // grid barrier arrivals (monotone)
+  unsigned long long pad0[31];
+  unsigned int abort;            // nonzero: every workgroup leaves
+  unsigned int error;            // DeviceError
+  unsigned long long pad1[31];
+  unsigned long long acc[3][16]; // rotating epoch accumulators, kNumAcc used
+  // results written by workgroup 0 at the end of a launch
+  long long sweeps;
+  long long outer_iters;
+  long long policy_changes_last;
+  long long recentrings;
+  double final_dv_inf;
+  double final_err_ref;
+  double shift;
+  int converged;
+  int pad2;
+  float dv_last;                 // last sweep's max |dV| as FP32 (mb_sweep)
+};
+
+struct KParams {
+  // the MDP
+  int32_t storage;
+  int32_t m;
+  int64_t n;
+  double gamma;
+  const float* P;          // dense [n][m][n]
+  const int64_t* row_ptr;  // CSR
+  const int32_t* col;
+  const float* val;
+  int32_t ell_k;           // constant row length (kEll), else 0
+  int32_t pad0;
+  const float* c32;        // plain costs [n*m]
+  double* ceff;            // shifted costs [n*m] (solvers), workspace
+  double* rho;             // row sums [n*m] (solvers), workspace
+  // vectors
+  float* vbuf0;            // caller's V
+  float* vbuf1;            // ping-pong partner, workspace
+  int32_t* policy;         // B_{mu,b} policy in; improvement out
+  int32_t* argmin_out;
+  const int32_t* perm;     // explicit order or null
+  const double* vref;       // FP64 reference values (measurement mode)
+  // schedule
+  int32_t task;
+  int32_t policy_sweep;    // mb_sweep with a policy
+  int64_t b;
+  uint64_t seed;
+  uint64_t first_sweep;
+  int64_t max_sweeps;      // VI
+  int64_t max_outer;       // MPI
+  int32_t K;               // MPI evaluation sweeps
+  int32_t policy_is_init;  // MPI
+  int32_t recentre_every;  // 0: plain costs, no shift
+  int32_t want_policy_out; // VI: greedy policy at the end into `policy`
+  double tol_dv;
+  double eps;
+  // decomposition
+  int32_t splits;          // dense: workgroups per state when b is small
+  int32_t pad1;
+  // workspace
+  Control* ctl;
+  int32_t* order;          // [3][n] sweep orders, by sweep index mod 3
+  float* partial;          // dense split partial sums
+  unsigned int* unit_count;// dense split arrival counters
+  unsigned long long timeout_ticks;
+};
+
+// Workspace layout, shared by the size query and the launches.
+struct WsLayout {
+  size_t ctl, unit_count, partial, order, vbuf1, ceff, rho, total;
+  size_t zero_bytes;  // prefix cleared before every launch (control + counters)
+};
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// max_units bounds the (state, split) units of one dense batch: b * splits
+// < b + blocks <= n + max_blocks.
+inline WsLayout ws_layout(int32_t storage, int64_t n, int32_t m, int64_t max_units) {
+  WsLayout w{};
+  size_t off = 0;
+  w.ctl = off;        off = align_up(off + sizeof(Control), 256);
+  w.unit_count = off;
+  if (storage == kDense) off = align_up(off + (size_t)max_units * sizeof(unsigned int), 256);
+  w.zero_bytes = off;
+  w.partial = off;
+  if (storage == kDense) off = align_up(off + (size_t)max_units * (size_t)m * sizeof(float), 256);
+  w.order = off;      off = align_up(off + 3 * (size_t)n * sizeof(int32_t), 256);
+  w.vbuf1 = off;      off = align_up(off + (size_t)n * sizeof(float), 256);
+  w.ceff = off;       off = align_up(off + (size_t)n * (size_t)m * sizeof(double), 256);
+  w.rho = off;        off = align_up(off + (size_t)n * (size_t)m * sizeof(double), 256);
+  w.total = off;
+  return w;
+}
+
+// Launch entry points implemented in mbdp_kernels.hip.
+struct LaunchShape {
+  int cus;            // compute units of the device
+  int blocks_per_cu;  // requested persistent workgroups per CU (clamped to occupancy)
+  int threads;        // threads per workgroup
+};
+
+constexpr int kMaxBlocksPerCu = 16;
+
+// Fills p.splits from the grid actually used and launches the persistent
+// kernel cooperatively.  Returns 0 or -1 with a message in err.
+int launch_solve(KParams p, LaunchShape shape, void* stream, char* err, size_t errlen);
+int launch_zero(void* ptr, size_t bytes, void* stream);
+int launch_permutation(int64_t n, uint64_t seed, uint64_t t, int32_t* out, void* stream);
+int launch_csr_inspect(const int64_t* row_ptr, const int32_t* col, int64_t rows, int64_t n,
+                       int64_t nnz, int64_t k, unsigned long long* flags, void* stream);
+int launch_validate(const KParams& p, double tol, unsigned long long* out, void* stream);
+
+}  // namespace mbdp

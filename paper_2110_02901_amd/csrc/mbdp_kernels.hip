@@ -1,0 +1,993 @@
+// HIP kernels of libmbdp for gfx950 (MI355X).
+//
+// One persistent, cooperatively launched kernel runs a whole call: one sweep
+// (mb_sweep), MB-VI (vi_solve) or MB-MPI (mpi_solve).  A sweep of the
+// mini-batch operator (Sec. III-A, eqs. (10)-(12)) processes the states in
+// the order sigma_t, cut into batches of b consecutive positions; the
+// states of one batch are computed in parallel from the values before the
+// batch and committed together, so later batches see them.  Between batches
+// every workgroup meets at a device-wide barrier (one per batch), instead
+// of one kernel launch per batch.
+//
+// Visibility of V across batches uses two buffers.  In the phase of batch k
+// the kernel reads buffer R (complete up to batch k-1) and writes into the
+// other buffer W the new values of batch k and a copy of batch k-1 (still
+// missing there).  After the barrier the roles swap.  No state of a batch
+// can therefore read a value of its own batch (Jacobi inside a batch, as
+// eq. (11) requires: M_b(i) holds only earlier batches).
+//
+// The hot loop is the row gather + dot product Q(s,a) = c(s,a) +
+// gamma * sum_s' P(s,a,s') V(s'):
+//  * dense: a workgroup per (state, column block), all m rows of the state
+//    streamed with non-temporal 16-byte loads, V reused from registers for
+//    the m rows, partial sums reduced through LDS (and, for small b, across
+//    workgroups with per-state arrival counters);
+//  * constant row length k (ELL): a wavefront per state, k/4 lanes per row,
+//    one 16-byte load of columns and one of weights per lane, V gathered;
+//  * general CSR: a wavefront per state, lanes striding over each row.
+// Dot products accumulate in FP32; cost, discount and the action minimum
+// are done in FP64 and the result rounded to FP32.
+//
+// The order of the next batch is computed during the current one and
+// stored, so its ALU work overlaps the memory stream.
+
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+
+#include "mbdp_device.h"
+#include "mbdp_internal.h"
+
+namespace mbdp {
+
+// ------------------------------------------------------------ accumulators
+
+struct Local {
+  double dv, err, wmax, wmin, resid;
+  unsigned long long changes;
+  __device__ __forceinline__ void reset() {
+    dv = 0.0;
+    err = 0.0;
+    resid = 0.0;
+    wmax = -INFINITY;
+    wmin = INFINITY;
+    changes = 0;
+  }
+};
+
+__device__ __forceinline__ void reset_slot(Control* ctl, int slot) {
+  for (int i = 0; i < kNumAcc; ++i) {
+    unsigned long long v = 0ull;
+    if (i == kAccWmin) v = ~0ull;
+    atomic_store_agent(&ctl->acc[slot][i], v);
+  }
+}
+
+// Block-wide reduction of the per-thread accumulators into epoch slot `slot`.
+__device__ __forceinline__ void flush_local(Local& L, Control* ctl, int slot) {
+  __shared__ double sh[16][5];
+  __shared__ unsigned long long shc[16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const double dv = wave_max_d(L.dv), err = wave_max_d(L.err), res = wave_max_d(L.resid);
+  const double wmax = wave_max_d(L.wmax), wmin = wave_min_d(L.wmin);
+  unsigned long long ch = L.changes;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) ch += __shfl_xor(ch, off);
+  if (lane == 0) {
+    sh[w][0] = dv;
+    sh[w][1] = err;
+    sh[w][2] = res;
+    sh[w][3] = wmax;
+    sh[w][4] = wmin;
+    shc[w] = ch;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = sh[0][0], b = sh[0][1], c = sh[0][2], d = sh[0][3], e = sh[0][4];
+    unsigned long long f = shc[0];
+    for (int i = 1; i < nw; ++i) {
+      a = fmax(a, sh[i][0]);
+      b = fmax(b, sh[i][1]);
+      c = fmax(c, sh[i][2]);
+      d = fmax(d, sh[i][3]);
+      e = fmin(e, sh[i][4]);
+      f += shc[i];
+    }
+    unsigned long long* acc = ctl->acc[slot];
+    if (a > 0.0) atomicMax(&acc[kAccDv], (unsigned long long)__double_as_longlong(a));
+    if (b > 0.0) atomicMax(&acc[kAccErr], (unsigned long long)__double_as_longlong(b));
+    if (c > 0.0) atomicMax(&acc[kAccResid], (unsigned long long)__double_as_longlong(c));
+    if (d > -INFINITY) atomicMax(&acc[kAccWmax], okey(d));
+    if (e < INFINITY) atomicMin(&acc[kAccWmin], okey(e));
+    if (f) atomicAdd(&acc[kAccChanges], f);
+  }
+  __syncthreads();
+  L.reset();
+}
+
+__device__ __forceinline__ double slot_double(Control* ctl, int slot, int i) {
+  return __longlong_as_double((long long)atomic_load_agent(&ctl->acc[slot][i]));
+}
+
+// ------------------------------------------------------------ per-state commit
+
+struct Ctx {
+  float* rd;   // read buffer: V before the current batch (complete)
+  float* wr;   // write buffer
+  double r;    // shift: V = W + r
+};
+
+__device__ __forceinline__ double cost_of(const KParams& p, int64_t row) {
+  return p.ceff ? p.ceff[row] : (double)p.c32[row];
+}
+
+// New value of state s from the FP64 bracket minimum q with action a.
+__device__ __forceinline__ void commit_sweep(const KParams& p, const Ctx& c, int32_t s, double q,
+                                             int a, Local& L) {
+  const float old = c.rd[s];
+  const float w = (float)q;
+  c.wr[s] = w;
+  if (p.argmin_out) p.argmin_out[s] = a;
+  L.dv = fmax(L.dv, fabs((double)w - (double)old));
+  if (p.vref) L.err = fmax(L.err, fabs(((double)w + c.r) - p.vref[s]));
+  L.wmax = fmax(L.wmax, (double)w);
+  L.wmin = fmin(L.wmin, (double)w);
+}
+
+// Policy improvement of state s (Algorithm 1): V is not written.
+__device__ __forceinline__ void commit_improve(const KParams& p, const Ctx& c, int32_t s, double q,
+                                               int a, bool count, Local& L) {
+  if (count && p.policy[s] != a) L.changes += 1;
+  p.policy[s] = a;
+  L.resid = fmax(L.resid, fabs(q - (double)c.rd[s]));
+}
+
+enum Mode : int { kModeMin = 0, kModePolicy = 1, kModeImprove = 2, kModeImproveCount = 3 };
+
+// ------------------------------------------------------------ dense engine
+
+// acc[r] += sum_{j in [j0, j1), this thread's columns} rows[r][j] * V[j].
+// Row bases are uniform across the workgroup and column offsets are 32-bit,
+// so every load is a scalar base plus one vector offset.
+template <int R, int VEC, int U>
+__device__ __forceinline__ void dense_dot(const float* __restrict__ rows, uint32_t n, int nrows,
+                                          const float* __restrict__ V, uint32_t j0, uint32_t j1,
+                                          float (&acc)[R]) {
+  const uint32_t step = blockDim.x * VEC;
+  for (uint32_t j = j0 + threadIdx.x * VEC; j < j1; j += step * U) {
+    if constexpr (VEC == 4) {
+      f4 v[U];
+      f4 x[U][R];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t jj = j + u * step;
+        const bool ok = jj < j1;
+        v[u] = ok ? *reinterpret_cast<const f4*>(V + jj) : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          x[u][r] = (ok && r < nrows)
+                        ? __builtin_nontemporal_load(
+                              reinterpret_cast<const f4*>(rows + (size_t)r * n + jj))
+                        : f4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          acc[r] = fmaf(x[u][r].x, v[u].x, acc[r]);
+          acc[r] = fmaf(x[u][r].y, v[u].y, acc[r]);
+          acc[r] = fmaf(x[u][r].z, v[u].z, acc[r]);
+          acc[r] = fmaf(x[u][r].w, v[u].w, acc[r]);
+        }
+    } else {
+      float v[U];
+      float x[U][R];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t jj = j + u * step;
+        const bool ok = jj < j1;
+        v[u] = ok ? V[jj] : 0.f;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          x[u][r] = (ok && r < nrows) ? __builtin_nontemporal_load(rows + (size_t)r * n + jj) : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = fmaf(x[u][r], v[u], acc[r]);
+    }
+  }
+}
+
+// out[r] (LDS) = block-wide sum of acc[r], r < R.  Deterministic order.
+template <int R>
+__device__ __forceinline__ void block_sum(float (&acc)[R], float* out) {
+  __shared__ float red[16][16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float v = wave_sum(acc[r]);
+    if (lane == 0) red[w][r] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < R) {
+    float s = 0.f;
+    for (int i = 0; i < nw; ++i) s += red[i][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+constexpr int kMaxActions = 1024;
+
+template <int R, int VEC>
+struct DenseEngine {
+  // Column range of split q of S, rounded to whole block-wide vector steps.
+  __device__ __forceinline__ static void split_range(uint32_t n, int S, int q, uint32_t& j0,
+                                                     uint32_t& j1) {
+    if (S == 1) {
+      j0 = 0;
+      j1 = n;
+      return;
+    }
+    const uint32_t quantum = blockDim.x * VEC;
+    uint32_t cs = (n + S - 1) / S;
+    cs = (cs + quantum - 1) / quantum * quantum;
+    j0 = min((uint32_t)q * cs, n);
+    j1 = min(j0 + cs, n);
+  }
+
+  // Processes this workgroup's units of one batch (ord == nullptr: the
+  // states are the positions themselves).
+  __device__ __forceinline__ static void batch(const KParams& p, const int32_t* ord, int64_t bk,
+                                               const Ctx& c, int mode, Local& L) {
+    __shared__ float s_sum[16];
+    __shared__ double s_q[kMaxActions];
+    __shared__ int s_last;
+    const int64_t n = p.n;
+    const int m = p.m;
+    const bool improve = mode >= kModeImprove;
+    const int S = improve ? 1 : p.splits;
+    const int64_t units = bk * S;
+    const int mr = (mode == kModePolicy) ? 1 : m;  // rows of a state that are read
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+      const int64_t i = u / S;
+      const int q = (int)(u % S);
+      const int32_t s = ord ? ord[i] : (int32_t)i;
+      uint32_t j0, j1;
+      split_range((uint32_t)n, S, q, j0, j1);
+      int apol = (mode == kModePolicy) ? p.policy[s] : 0;
+      if (apol < 0 || apol >= m) {
+        if (threadIdx.x == 0) raise_abort(p.ctl, kDevBadPolicy);
+        apol = 0;
+      }
+      // 1. partial dot products of the m (or 1) rows over [j0, j1)
+      if (mode == kModePolicy) {
+        float acc[1] = {0.f};
+        dense_dot<1, VEC, (VEC == 4 ? 8 : 16)>(p.P + ((size_t)s * m + apol) * (size_t)n,
+                                               (uint32_t)n, 1, c.rd, j0, j1, acc);
+        block_sum<1>(acc, s_sum);
+        if (threadIdx.x == 0) {
+          if (S == 1)
+            s_q[0] = cost_of(p, (int64_t)s * m + apol) + p.gamma * (double)s_sum[0];
+          else
+            p.partial[(size_t)(i * S + q)] = s_sum[0];
+        }
+      } else {
+        for (int a0 = 0; a0 < m; a0 += R) {
+          const int nrows = min(R, m - a0);
+          float acc[R];
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[r] = 0.f;
+          dense_dot<R, VEC, (VEC == 4 ? (R >= 16 ? 1 : 16 / R) : 4)>(
+              p.P + ((size_t)s * m + a0) * (size_t)n, (uint32_t)n, nrows, c.rd, j0, j1, acc);
+          block_sum<R>(acc, s_sum);
+          if (threadIdx.x < nrows) {
+            const int a = a0 + threadIdx.x;
+            if (S == 1)
+              s_q[a] = cost_of(p, (int64_t)s * m + a) + p.gamma * (double)s_sum[threadIdx.x];
+            else
+              p.partial[(size_t)(i * S + q) * m + a] = s_sum[threadIdx.x];
+          }
+        }
+      }
+      // 2. combine the splits: the last workgroup to arrive finishes the state
+      if (S > 1) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          const unsigned prev = atomicAdd(&p.unit_count[i], 1u);
+          int last = prev == (unsigned)(S - 1);
+          if (last) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            p.unit_count[i] = 0u;  // ready for the next batch using slot i
+          }
+          s_last = last;
+        }
+        __syncthreads();
+        if (!s_last) continue;
+        for (int a = threadIdx.x; a < mr; a += blockDim.x) {
+          double sum = 0.0;
+          for (int qq = 0; qq < S; ++qq) sum += (double)p.partial[(size_t)(i * S + qq) * mr + a];
+          const int act = (mode == kModePolicy) ? apol : a;
+          s_q[a] = cost_of(p, (int64_t)s * m + act) + p.gamma * sum;
+        }
+      }
+      __syncthreads();
+      // 3. action minimum (lowest index on ties) and commit, in wave 0
+      if (threadIdx.x < kWave) {
+        double qv = INFINITY;
+        int av = 0x7fffffff;
+        if (mode == kModePolicy) {
+          qv = s_q[0];
+          av = apol;
+        } else {
+          for (int a = threadIdx.x; a < m; a += kWave) {
+            const double x = s_q[a];
+            if (x < qv) {  // strictly smaller keeps the lowest index per lane
+              qv = x;
+              av = a;
+            }
+          }
+          wave_argmin(qv, av);
+          if (av == 0x7fffffff) av = 0;
+        }
+        if (threadIdx.x == 0) {
+          if (improve)
+            commit_improve(p, c, s, qv, av, mode == kModeImproveCount, L);
+          else
+            commit_sweep(p, c, s, qv, av, L);
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // rho(s,a) = sum_s' P(s,a,s') in FP64, one wavefront per row.
+  __device__ __forceinline__ static void row_sums(const KParams& p) {
+    const int64_t rows = p.n * p.m;
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t r = gw; r < rows; r += nw) {
+      const float* row = p.P + (size_t)r * (size_t)p.n;
+      double s = 0.0;
+      for (int64_t j = lane; j < p.n; j += kWave) s += (double)__builtin_nontemporal_load(row + j);
+      s = wave_sum_d(s);
+      if (lane == 0) p.rho[r] = s;
+    }
+  }
+};
+
+// ------------------------------------------------------------ ELL engine
+//
+// Constant row length k, k % 4 == 0, k <= 256.  A row is served by LPR =
+// (k/4 rounded up to a power of two) lanes; a wavefront covers RPP = 64/LPR
+// rows per pass.  In the minimum modes a wavefront serves UNR states at a
+// time; in the policy mode each lane group serves its own state.
+template <int UNR>
+struct EllEngine {
+  __device__ __forceinline__ static int lanes_per_row(int k) {
+    int lpr = 1;
+    while (lpr * 4 < k) lpr <<= 1;
+    return lpr;
+  }
+
+  __device__ __forceinline__ static void batch(const KParams& p, const int32_t* ord, int64_t bk,
+                                               const Ctx& c, int mode, Local& L) {
+    const int m = p.m, k = p.ell_k;
+    const int lpr = lanes_per_row(k), rpp = kWave / lpr;
+    const int lane = threadIdx.x & 63, g = lane / lpr, l = lane % lpr;
+    const bool lane_has_data = l * 4 < k;
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const bool improve = mode >= kModeImprove;
+    if (mode == kModePolicy) {
+      const int64_t per_unit = (int64_t)rpp * UNR;
+      const int64_t units = (bk + per_unit - 1) / per_unit;
+      for (int64_t u = gw; u < units; u += nw) {
+        int32_t s[UNR];
+        int a[UNR];
+        i4 cc[UNR];
+        f4 vv[UNR];
+#pragma unroll
+        for (int x = 0; x < UNR; ++x) {
+          const int64_t pos = u * per_unit + (int64_t)x * rpp + g;
+          s[x] = pos < bk ? (ord ? ord[pos] : (int32_t)pos) : -1;
+        }
+#pragma unroll
+        for (int x = 0; x < UNR; ++x) {
+          a[x] = s[x] >= 0 ? p.policy[s[x]] : 0;
+          if (a[x] < 0 || a[x] >= m) {
+            raise_abort(p.ctl, kDevBadPolicy);
+            a[x] = 0;
+          }
+          if (s[x] >= 0 && lane_has_data) {
+            const size_t e = ((size_t)s[x] * m + a[x]) * (size_t)k + (size_t)l * 4;
+            cc[x] = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e));
+            vv[x] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e));
+          } else {
+            cc[x] = i4{0, 0, 0, 0};
+            vv[x] = f4{0.f, 0.f, 0.f, 0.f};
+          }
+        }
+#pragma unroll
+        for (int x = 0; x < UNR; ++x) {
+          float part = vv[x].x * c.rd[cc[x].x];
+          part = fmaf(vv[x].y, c.rd[cc[x].y], part);
+          part = fmaf(vv[x].z, c.rd[cc[x].z], part);
+          part = fmaf(vv[x].w, c.rd[cc[x].w], part);
+          for (int off = lpr >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
+          if (l == 0 && s[x] >= 0) {
+            const double q = cost_of(p, (int64_t)s[x] * m + a[x]) + p.gamma * (double)part;
+            commit_sweep(p, c, s[x], q, a[x], L);
+          }
+        }
+      }
+      return;
+    }
+    const int64_t units = (bk + UNR - 1) / UNR;
+    for (int64_t u = gw; u < units; u += nw) {
+      int32_t s[UNR];
+      double qb[UNR];
+      int ab[UNR];
+#pragma unroll
+      for (int x = 0; x < UNR; ++x) {
+        const int64_t pos = u * UNR + x;
+        s[x] = pos < bk ? (ord ? ord[pos] : (int32_t)pos) : -1;
+        qb[x] = INFINITY;
+        ab[x] = 0x7fffffff;
+      }
+      for (int a0 = 0; a0 < m; a0 += rpp) {
+        const int a = a0 + g;
+        const bool row_ok = a < m && lane_has_data;
+        i4 cc[UNR];
+        f4 vv[UNR];
+#pragma unroll
+        for (int x = 0; x < UNR; ++x) {
+          if (row_ok && s[x] >= 0) {
+            const size_t e = ((size_t)s[x] * m + a) * (size_t)k + (size_t)l * 4;
+            cc[x] = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e));
+            vv[x] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e));
+          } else {
+            cc[x] = i4{0, 0, 0, 0};
+            vv[x] = f4{0.f, 0.f, 0.f, 0.f};
+          }
+        }
+#pragma unroll
+        for (int x = 0; x < UNR; ++x) {
+          float part = vv[x].x * c.rd[cc[x].x];
+          part = fmaf(vv[x].y, c.rd[cc[x].y], part);
+          part = fmaf(vv[x].z, c.rd[cc[x].z], part);
+          part = fmaf(vv[x].w, c.rd[cc[x].w], part);
+          for (int off = lpr >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
+          double q = INFINITY;
+          int aq = 0x7fffffff;
+          if (a < m && s[x] >= 0) {
+            q = cost_of(p, (int64_t)s[x] * m + a) + p.gamma * (double)part;
+            aq = a;
+          }
+          wave_argmin(q, aq, lpr);
+          if (q < qb[x] || (q == qb[x] && aq < ab[x])) {
+            qb[x] = q;
+            ab[x] = aq;
+          }
+        }
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int x = 0; x < UNR; ++x) {
+          if (s[x] < 0) continue;
+          const int av = ab[x] == 0x7fffffff ? 0 : ab[x];
+          if (improve)
+            commit_improve(p, c, s[x], qb[x], av, mode == kModeImproveCount, L);
+          else
+            commit_sweep(p, c, s[x], qb[x], av, L);
+        }
+      }
+    }
+  }
+
+  // rho = row sums in FP64, one thread per row.
+  __device__ __forceinline__ static void row_sums(const KParams& p) {
+    const int64_t rows = p.n * p.m;
+    const int k = p.ell_k;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows;
+         r += (int64_t)gridDim.x * blockDim.x) {
+      double s = 0.0;
+      for (int e = 0; e < k; ++e) s += (double)p.val[(size_t)r * k + e];
+      p.rho[r] = s;
+    }
+  }
+};
+
+// ------------------------------------------------------------ general CSR engine
+
+struct CsrEngine {
+  __device__ __forceinline__ static void batch(const KParams& p, const int32_t* ord, int64_t bk,
+                                               const Ctx& c, int mode, Local& L) {
+    const int m = p.m;
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const bool improve = mode >= kModeImprove;
+    for (int64_t u = gw; u < bk; u += nw) {
+      const int32_t s = ord ? ord[u] : (int32_t)u;
+      double qb = INFINITY;
+      int ab = 0x7fffffff;
+      int a_lo = mode == kModePolicy ? p.policy[s] : 0;
+      if (a_lo < 0 || a_lo >= m) {
+        if (lane == 0) raise_abort(p.ctl, kDevBadPolicy);
+        a_lo = 0;
+      }
+      const int a_hi = mode == kModePolicy ? a_lo + 1 : m;
+      for (int a = a_lo; a < a_hi; ++a) {
+        const int64_t row = (int64_t)s * m + a;
+        const int64_t e0 = p.row_ptr[row], e1 = p.row_ptr[row + 1];
+        float part = 0.f;
+        for (int64_t e = e0 + lane; e < e1; e += kWave)
+          part = fmaf(__builtin_nontemporal_load(p.val + e), c.rd[p.col[e]], part);
+        part = wave_sum(part);
+        const double q = cost_of(p, row) + p.gamma * (double)part;
+        if (q < qb) {
+          qb = q;
+          ab = a;
+        }
+      }
+      if (ab == 0x7fffffff) ab = a_lo;
+      if (lane == 0) {
+        if (improve)
+          commit_improve(p, c, s, qb, ab, mode == kModeImproveCount, L);
+        else
+          commit_sweep(p, c, s, qb, ab, L);
+      }
+    }
+  }
+
+  __device__ __forceinline__ static void row_sums(const KParams& p) {
+    const int64_t rows = p.n * p.m;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows;
+         r += (int64_t)gridDim.x * blockDim.x) {
+      double s = 0.0;
+      for (int64_t e = p.row_ptr[r]; e < p.row_ptr[r + 1]; ++e) s += (double)p.val[e];
+      p.rho[r] = s;
+    }
+  }
+};
+
+// ------------------------------------------------------------ the persistent kernel
+
+struct Driver {
+  const KParams& p;
+  GridBarrier g;
+  Local L;
+  float* buf0;
+  float* buf1;
+  int64_t phase;          // batches processed (parity selects the read buffer)
+  const int32_t* prev_order;
+  int64_t prev_count;     // states of the previous batch still to copy forward
+  double r;               // V = W + r
+  unsigned epoch;         // sweeps + improvement passes, selects accumulator slot
+  int64_t gtid, gthreads;
+
+  __device__ __forceinline__ explicit Driver(const KParams& kp) : p(kp) {
+    g.ctl = p.ctl;
+    g.target = 0;
+    g.nblocks = gridDim.x;
+    g.timeout = p.timeout_ticks;
+    L.reset();
+    buf0 = p.vbuf0;
+    buf1 = p.vbuf1;
+    phase = 0;
+    prev_order = nullptr;
+    prev_count = 0;
+    r = 0.0;
+    epoch = 0;
+    gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    gthreads = (int64_t)gridDim.x * blockDim.x;
+  }
+
+  // order[t % 3][pos] for pos in [begin, begin + count): sigma_t or perm.
+  __device__ __forceinline__ void fill_order(uint64_t t, int64_t begin, int64_t count) {
+    int32_t* dst = p.order + (size_t)(t % 3) * (size_t)p.n;
+    if (p.perm) {
+      for (int64_t i = gtid; i < count; i += gthreads) {
+        const int32_t v = p.perm[begin + i];
+        if (v < 0 || (int64_t)v >= p.n) {
+          raise_abort(p.ctl, kDevBadPerm);
+          dst[begin + i] = 0;
+        } else {
+          dst[begin + i] = v;
+        }
+      }
+      return;
+    }
+    const OrderKey key = make_order_key(p.n, p.seed, t);
+    for (int64_t i = gtid; i < count; i += gthreads)
+      dst[begin + i] = (int32_t)sweep_order_at((uint32_t)(begin + i), key);
+  }
+
+  // buffer holding V before the current batch (complete) / the other one
+  __device__ __forceinline__ float* rd_buf() const { return (phase & 1) ? buf1 : buf0; }
+  __device__ __forceinline__ float* wr_buf() const { return (phase & 1) ? buf0 : buf1; }
+
+  __device__ __forceinline__ int slot() const { return (int)(epoch % 3); }
+
+  template <class Eng>
+  __device__ __forceinline__ bool sweep(uint64_t t, int mode) {
+    const int64_t n = p.n, b = p.b, nb = (n + b - 1) / b;
+    if (blockIdx.x == 0 && threadIdx.x == 0) reset_slot(p.ctl, (int)((epoch + 1) % 3));
+    const int32_t* ord = p.order + (size_t)(t % 3) * (size_t)n;
+    for (int64_t k = 0; k < nb; ++k) {
+      const int64_t kb = k * b, bk = min(b, n - kb);
+      Ctx c{rd_buf(), wr_buf(), r};
+      for (int64_t i = gtid; i < prev_count; i += gthreads) {
+        const int32_t s = prev_order[i];
+        c.wr[s] = c.rd[s];
+      }
+      if (k + 1 < nb)
+        fill_order(t, kb + b, min(b, n - kb - b));
+      else
+        fill_order(t + 1, 0, min(b, n));
+      Eng::batch(p, ord + kb, bk, c, mode, L);
+      prev_order = ord + kb;
+      prev_count = bk;
+      if (k == nb - 1) flush_local(L, p.ctl, slot());
+      if (!grid_sync(g)) return false;
+      ++phase;
+    }
+    ++epoch;
+    return true;
+  }
+
+  template <class Eng>
+  __device__ __forceinline__ bool improve(bool count) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) reset_slot(p.ctl, (int)((epoch + 1) % 3));
+    Ctx c{rd_buf(), wr_buf(), r};
+    Eng::batch(p, nullptr, p.n, c, count ? kModeImproveCount : kModeImprove, L);
+    flush_local(L, p.ctl, slot());
+    if (!grid_sync(g)) return false;
+    ++epoch;
+    return true;
+  }
+
+  // Shift both buffers by the midpoint of the last sweep's values and
+  // rebuild the shifted costs (re-centring; exact in real arithmetic).
+  __device__ __forceinline__ bool recentre(int last_slot, long long& count) {
+    const double wmax = okey_value(atomic_load_agent(&p.ctl->acc[last_slot][kAccWmax]));
+    const double wmin = okey_value(atomic_load_agent(&p.ctl->acc[last_slot][kAccWmin]));
+    const double delta = 0.5 * (wmax + wmin);
+    if (!isfinite(delta) || delta == 0.0) return true;
+    r += delta;
+    for (int64_t s = gtid; s < p.n; s += gthreads) {
+      buf0[s] = (float)((double)buf0[s] - delta);
+      buf1[s] = (float)((double)buf1[s] - delta);
+    }
+    const int64_t rows = p.n * p.m;
+    for (int64_t i = gtid; i < rows; i += gthreads)
+      p.ceff[i] = (double)p.c32[i] - r + p.gamma * r * p.rho[i];
+    ++count;
+    return grid_sync(g);
+  }
+
+  // Final V into the caller's buffer (V = W + r) and the statistics.
+  __device__ __forceinline__ void finish(long long sweeps, long long outer, long long changes_last,
+                         long long recentrings, double last_dv, double last_err, int converged) {
+    float* cur = rd_buf();
+    if (r != 0.0) {
+      for (int64_t s = gtid; s < p.n; s += gthreads) p.vbuf0[s] = (float)((double)cur[s] + r);
+    } else if (cur != p.vbuf0) {
+      for (int64_t i = gtid; i < prev_count; i += gthreads) {
+        const int32_t s = prev_order[i];
+        p.vbuf0[s] = cur[s];
+      }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      Control* ctl = p.ctl;
+      ctl->sweeps = sweeps;
+      ctl->outer_iters = outer;
+      ctl->policy_changes_last = changes_last;
+      ctl->recentrings = recentrings;
+      ctl->final_dv_inf = last_dv;
+      ctl->final_err_ref = last_err;
+      ctl->shift = r;
+      ctl->converged = converged;
+      ctl->dv_last = (float)last_dv;
+    }
+  }
+};
+
+template <class Eng, int TASK>
+__global__ void __launch_bounds__(1024) solve_kernel(KParams p) {
+  Driver d(p);
+  const int64_t n = p.n;
+  uint64_t t = p.first_sweep;
+  // prologue: second buffer, row sums and shifted costs, first order
+  for (int64_t s = d.gtid; s < n; s += d.gthreads) p.vbuf1[s] = p.vbuf0[s];
+  if (TASK != kTaskSweep && p.recentre_every > 0) {
+    Eng::row_sums(p);
+    for (int64_t i = d.gtid; i < n * p.m; i += d.gthreads) p.ceff[i] = (double)p.c32[i];
+  }
+  d.fill_order(t, 0, min(p.b, n));
+  if (blockIdx.x == 0 && threadIdx.x == 0) reset_slot(p.ctl, 0);
+  if (!grid_sync(d.g)) return;
+
+  long long sweeps = 0, outer = 0, changes_last = -1, recentrings = 0;
+  double last_dv = NAN, last_err = NAN;
+  int converged = 0;
+
+  if constexpr (TASK == kTaskSweep) {
+    if (!d.template sweep<Eng>(t, p.policy_sweep ? kModePolicy : kModeMin)) return;
+    sweeps = 1;
+    last_dv = slot_double(p.ctl, (int)((d.epoch - 1) % 3), kAccDv);
+    converged = 1;
+  } else if constexpr (TASK == kTaskVI) {
+    while (true) {
+      if (!d.template sweep<Eng>(t, kModeMin)) return;
+      ++t;
+      ++sweeps;
+      const int sl = (int)((d.epoch - 1) % 3);
+      last_dv = slot_double(p.ctl, sl, kAccDv);
+      bool stop = p.tol_dv >= 0.0 && last_dv <= p.tol_dv;
+      if (p.vref) {
+        last_err = slot_double(p.ctl, sl, kAccErr);
+        stop = stop || last_err <= p.eps;
+      }
+      if (stop) {
+        converged = 1;
+        break;
+      }
+      if (sweeps >= p.max_sweeps) break;
+      if (p.recentre_every > 0 && sweeps % p.recentre_every == 0)
+        if (!d.recentre(sl, recentrings)) return;
+    }
+    if (p.want_policy_out)
+      if (!d.template improve<Eng>(false)) return;
+  } else {  // MPI, Algorithm 1
+    if (!p.policy_is_init)
+      if (!d.template improve<Eng>(false)) return;
+    bool done = false;
+    while (!done) {
+      for (int k = 0; k < p.K; ++k) {
+        if (!d.template sweep<Eng>(t, kModePolicy)) return;
+        ++t;
+        ++sweeps;
+        const int sl = (int)((d.epoch - 1) % 3);
+        if (p.vref) {
+          last_err = slot_double(p.ctl, sl, kAccErr);
+          if (last_err <= p.eps) {
+            converged = 1;
+            done = true;
+            break;
+          }
+        }
+        if (p.recentre_every > 0 && sweeps % p.recentre_every == 0)
+          if (!d.recentre(sl, recentrings)) return;
+      }
+      if (done) break;
+      if (!d.template improve<Eng>(true)) return;
+      ++outer;
+      const int sl = (int)((d.epoch - 1) % 3);
+      changes_last = (long long)atomic_load_agent(&p.ctl->acc[sl][kAccChanges]);
+      last_dv = slot_double(p.ctl, sl, kAccResid);
+      if (changes_last == 0 && p.tol_dv >= 0.0 && last_dv <= p.tol_dv) {
+        converged = 1;
+        break;
+      }
+      if (outer >= p.max_outer) break;
+    }
+  }
+  d.finish(sweeps, outer, changes_last, recentrings, last_dv, last_err, converged);
+}
+
+// ------------------------------------------------------------ small kernels
+
+__global__ void zero_kernel(unsigned int* p, size_t words) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+__global__ void permutation_kernel(int64_t n, uint64_t seed, uint64_t t, int32_t* out) {
+  const OrderKey key = make_order_key(n, seed, t);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (int32_t)sweep_order_at((uint32_t)i, key);
+}
+
+// flags[0]: rows whose length differs from k; flags[1]: decreasing row_ptr
+// entries or entries outside [0, nnz]; flags[2]: row_ptr[0] != 0 or
+// row_ptr[rows] != nnz; flags[3]: columns outside [0, n).
+__global__ void csr_inspect_kernel(const int64_t* row_ptr, const int32_t* col, int64_t rows,
+                                   int64_t n, int64_t nnz, int64_t k, unsigned long long* flags) {
+  unsigned long long not_k = 0, bad_ptr = 0, bad_col = 0;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = tid; r < rows; r += nth) {
+    const int64_t a = row_ptr[r], b = row_ptr[r + 1];
+    not_k += (b - a) != k;
+    bad_ptr += (b < a) || a < 0 || b > nnz;
+  }
+  for (int64_t e = tid; e < nnz; e += nth) {
+    const int32_t c = col[e];
+    bad_col += c < 0 || (int64_t)c >= n;
+  }
+  if (not_k) atomicAdd(&flags[0], not_k);
+  if (bad_ptr) atomicAdd(&flags[1], bad_ptr);
+  if (bad_col) atomicAdd(&flags[3], bad_col);
+  if (tid == 0)
+    if (row_ptr[0] != 0 || row_ptr[rows] != nnz) atomicAdd(&flags[2], 1ull);
+}
+
+// out: [0] bad probability, [1] bad row sum, [2] empty rows, [3] bad column,
+// [4] bad row_ptr, [5] bad cost, [6] no admissible action, [7] max |rowsum-1|
+// (double bits).
+__global__ void validate_kernel(KParams p, double tol, unsigned long long* out) {
+  const int64_t rows = p.n * p.m;
+  unsigned long long bad_p = 0, bad_sum = 0, empty = 0, bad_col = 0, bad_ptr = 0;
+  double dev = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    if (p.storage == kDense) {
+      const float* row = p.P + (size_t)r * (size_t)p.n;
+      for (int64_t j = 0; j < p.n; ++j) {
+        const float x = row[j];
+        if (!(x >= 0.f) || isinf(x)) ++bad_p;
+        s += (double)x;
+      }
+    } else {
+      const int64_t e0 = p.row_ptr[r], e1 = p.row_ptr[r + 1];
+      if (e1 < e0) ++bad_ptr;
+      if (e1 <= e0) ++empty;
+      for (int64_t e = e0; e < e1; ++e) {
+        const float x = p.val[e];
+        if (!(x >= 0.f) || isinf(x)) ++bad_p;
+        const int32_t cidx = p.col[e];
+        if (cidx < 0 || (int64_t)cidx >= p.n) ++bad_col;
+        s += (double)x;
+      }
+    }
+    const double d = fabs(s - 1.0);
+    if (!(d <= tol)) ++bad_sum;
+    if (d > dev || isnan(d)) dev = isnan(d) ? INFINITY : d;
+  }
+  unsigned long long bad_cost = 0, no_adm = 0;
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < p.n;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    int finite = 0;
+    for (int a = 0; a < p.m; ++a) {
+      const float x = p.c32[s * p.m + a];
+      if (isnan(x) || (isinf(x) && x < 0.f)) ++bad_cost;
+      if (isfinite(x)) finite = 1;
+    }
+    if (!finite) ++no_adm;
+  }
+  if (bad_p) atomicAdd(&out[0], bad_p);
+  if (bad_sum) atomicAdd(&out[1], bad_sum);
+  if (empty) atomicAdd(&out[2], empty);
+  if (bad_col) atomicAdd(&out[3], bad_col);
+  if (bad_ptr) atomicAdd(&out[4], bad_ptr);
+  if (bad_cost) atomicAdd(&out[5], bad_cost);
+  if (no_adm) atomicAdd(&out[6], no_adm);
+  if (dev > 0.0) atomicMax(&out[7], (unsigned long long)__double_as_longlong(dev));
+}
+
+// ------------------------------------------------------------ launchers
+
+// Result words of the CSR structure inspection done by mdp_create_csr (the
+// only device memory the library owns; callers serialise its use).
+__device__ unsigned long long g_inspect_flags[8];
+
+int inspect_flags_ptr(void** out) {
+  return (int)hipGetSymbolAddress(out, HIP_SYMBOL(g_inspect_flags));
+}
+
+
+typedef void (*SolveFn)(KParams);
+
+template <class Eng>
+static SolveFn solve_fn(int task) {
+  if (task == kTaskSweep) return &solve_kernel<Eng, kTaskSweep>;
+  if (task == kTaskVI) return &solve_kernel<Eng, kTaskVI>;
+  return &solve_kernel<Eng, kTaskMPI>;
+}
+
+// Picks the kernel instantiation for the launch.
+static SolveFn pick(const KParams& p, int units_per_wave_hint) {
+  if (p.storage == kDense) {
+    const bool vec = p.n % 4 == 0;
+    const int m = p.m;
+    if (vec) {
+      if (m >= 16) return solve_fn<DenseEngine<16, 4>>(p.task);
+      if (m >= 8) return solve_fn<DenseEngine<8, 4>>(p.task);
+      if (m >= 4) return solve_fn<DenseEngine<4, 4>>(p.task);
+      if (m >= 2) return solve_fn<DenseEngine<2, 4>>(p.task);
+      return solve_fn<DenseEngine<1, 4>>(p.task);
+    }
+    if (m >= 16) return solve_fn<DenseEngine<16, 1>>(p.task);
+    if (m >= 8) return solve_fn<DenseEngine<8, 1>>(p.task);
+    if (m >= 4) return solve_fn<DenseEngine<4, 1>>(p.task);
+    if (m >= 2) return solve_fn<DenseEngine<2, 1>>(p.task);
+    return solve_fn<DenseEngine<1, 1>>(p.task);
+  }
+  if (p.storage == kEll) {
+    if (units_per_wave_hint >= 4) return solve_fn<EllEngine<4>>(p.task);
+    if (units_per_wave_hint >= 2) return solve_fn<EllEngine<2>>(p.task);
+    return solve_fn<EllEngine<1>>(p.task);
+  }
+  return solve_fn<CsrEngine>(p.task);
+}
+
+int launch_solve(KParams p, LaunchShape shape, void* stream, char* err, size_t errlen) {
+  const int waves_per_block = shape.threads / kWave;
+  // ELL: states per wavefront iteration from the batch size and a full grid
+  const int64_t waves_guess = (int64_t)shape.cus * shape.blocks_per_cu * waves_per_block;
+  const int64_t per_wave = waves_guess > 0 ? p.b / waves_guess : 1;
+  SolveFn f = pick(p, (int)(per_wave > 4 ? 4 : per_wave));
+  int occ = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &occ, reinterpret_cast<const void*>(f), shape.threads, 0);
+  if (e != hipSuccess || occ < 1) {
+    snprintf(err, errlen, "occupancy query failed (%d blocks/CU): %s", occ, hipGetErrorString(e));
+    return -1;
+  }
+  const int bpc = shape.blocks_per_cu < occ ? shape.blocks_per_cu : occ;
+  const int blocks = shape.cus * bpc;
+  // dense: split the columns of a state over several workgroups when the
+  // batch has fewer states than there are workgroups
+  p.splits = 1;
+  if (p.storage == kDense && p.b < blocks) p.splits = (int)((blocks + p.b - 1) / p.b);
+  void* args[] = {&p};
+  e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(f), dim3(blocks),
+                                 dim3(shape.threads), args, 0,
+                                 reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    snprintf(err, errlen, "cooperative launch (%d x %d) failed: %s", blocks, shape.threads,
+             hipGetErrorString(e));
+    return -1;
+  }
+  return 0;
+}
+
+int launch_zero(void* ptr, size_t bytes, void* stream) {
+  const size_t words = bytes / 4;
+  int blocks = (int)((words + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(stream), static_cast<unsigned int*>(ptr), words);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_permutation(int64_t n, uint64_t seed, uint64_t t, int32_t* out, void* stream) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(permutation_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(stream), n, seed, t, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_csr_inspect(const int64_t* row_ptr, const int32_t* col, int64_t rows, int64_t n,
+                       int64_t nnz, int64_t k, unsigned long long* flags, void* stream) {
+  int64_t work = rows > nnz ? rows : nnz;
+  int64_t blocks = (work + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(csr_inspect_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(stream), row_ptr, col, rows, n, nnz, k, flags);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_validate(const KParams& p, double tol, unsigned long long* out, void* stream) {
+  int64_t rows = p.n * p.m;
+  int64_t blocks = (rows + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(validate_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(stream), p, tol, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace mbdp

@@ -1,0 +1,471 @@
+// Host runtime of libmbdp: the C-ABI declared in include/mbdp.h.
+//
+// Every entry point checks its arguments before any device work, maps HIP
+// failures to MBDP_ERR_HIP with a message, and never throws.  The library
+// allocates no device memory: scratch space is the caller's workspace, and
+// the one tiny result buffer of mdp_create_csr is a file-scope device array.
+
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "mbdp.h"
+#include "mbdp_internal.h"
+
+using namespace mbdp;
+
+struct mbdp_mdp {
+  int32_t storage;
+  int32_t m;
+  int64_t n;
+  double gamma;
+  const float* P;
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const float* val;
+  int64_t nnz;
+  int32_t ell_k;
+  const float* c;
+  int device;
+  int cus;
+  unsigned long long wall_khz;
+  mbdp_tuning tuning;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+mbdp_status fail(mbdp_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define MBDP_HIP(expr)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess) return fail(MBDP_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int64_t kMaxStates = (int64_t)1 << 31;  // state indices are int32
+constexpr int32_t kMaxDenseActions = 1024;        // LDS holds one Q per action
+constexpr double kBarrierTimeoutSeconds = 30.0;
+
+bool gamma_ok(double g) { return isfinite(g) && g > 0.0 && g < 1.0; }
+
+mbdp_status query_device(mbdp_mdp* h) {
+  MBDP_HIP(hipGetDevice(&h->device));
+  int cus = 0, khz = 0, coop = 0;
+  MBDP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+  MBDP_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device));
+  MBDP_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, h->device));
+  if (!coop) return fail(MBDP_ERR_UNSUPPORTED, "device %d has no cooperative launch", h->device);
+  if (cus < 1) return fail(MBDP_ERR_HIP, "device reports %d compute units", cus);
+  h->cus = cus;
+  h->wall_khz = khz > 0 ? (unsigned long long)khz : 100000ull;
+  return MBDP_OK;
+}
+
+int64_t max_units(const mbdp_mdp* h) { return h->n + (int64_t)h->cus * kMaxBlocksPerCu; }
+
+WsLayout layout(const mbdp_mdp* h) { return ws_layout(h->storage, h->n, h->m, max_units(h)); }
+
+mbdp_status check_ws(const mbdp_mdp* h, void* ws, size_t bytes) {
+  const WsLayout w = layout(h);
+  if (!ws) return fail(MBDP_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", w.total);
+  if (((uintptr_t)ws) % 256) return fail(MBDP_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  if (bytes < w.total)
+    return fail(MBDP_ERR_WORKSPACE, "workspace has %zu bytes, need %zu", bytes, w.total);
+  return MBDP_OK;
+}
+
+LaunchShape shape_of(const mbdp_mdp* h) {
+  LaunchShape s;
+  s.cus = h->cus;
+  s.threads = h->storage == kDense ? 512 : 256;
+  s.blocks_per_cu = h->storage == kDense ? 2 : 8;
+  if (h->tuning.threads_per_block == 256 || h->tuning.threads_per_block == 512 ||
+      h->tuning.threads_per_block == 1024)
+    s.threads = h->tuning.threads_per_block;
+  if (h->tuning.blocks_per_cu > 0)
+    s.blocks_per_cu =
+        h->tuning.blocks_per_cu < kMaxBlocksPerCu ? h->tuning.blocks_per_cu : kMaxBlocksPerCu;
+  return s;
+}
+
+int recentre_interval(const mbdp_mdp* h) {
+  if (h->tuning.recentre_every < 0) return 0;
+  return h->tuning.recentre_every > 0 ? h->tuning.recentre_every : 32;
+}
+
+KParams base_params(const mbdp_mdp* h, void* ws, float* V, int64_t b) {
+  const WsLayout w = layout(h);
+  char* base = static_cast<char*>(ws);
+  KParams p{};
+  p.storage = h->storage;
+  p.m = h->m;
+  p.n = h->n;
+  p.gamma = h->gamma;
+  p.P = h->P;
+  p.row_ptr = h->row_ptr;
+  p.col = h->col;
+  p.val = h->val;
+  p.ell_k = h->ell_k;
+  p.c32 = h->c;
+  p.vbuf0 = V;
+  p.vbuf1 = reinterpret_cast<float*>(base + w.vbuf1);
+  p.b = b;
+  p.ctl = reinterpret_cast<Control*>(base + w.ctl);
+  p.order = reinterpret_cast<int32_t*>(base + w.order);
+  p.partial = reinterpret_cast<float*>(base + w.partial);
+  p.unit_count = reinterpret_cast<unsigned int*>(base + w.unit_count);
+  p.timeout_ticks = (unsigned long long)(kBarrierTimeoutSeconds * 1000.0 * (double)h->wall_khz);
+  p.tol_dv = -1.0;
+  p.splits = 1;
+  return p;
+}
+
+mbdp_status launch(const mbdp_mdp* h, const KParams& p, void* ws, hipStream_t stream) {
+  const WsLayout w = layout(h);
+  if (launch_zero(ws, w.zero_bytes, stream) != 0)
+    return fail(MBDP_ERR_HIP, "workspace clear failed: %s", hipGetErrorString(hipGetLastError()));
+  char err[256] = {0};
+  if (launch_solve(p, shape_of(h), stream, err, sizeof err) != 0)
+    return fail(MBDP_ERR_HIP, "%s", err);
+  return MBDP_OK;
+}
+
+const char* device_error_text(unsigned code) {
+  switch (code) {
+    case kDevBadPerm: return "explicit order has an entry outside [0, n)";
+    case kDevBarrierTimeout: return "grid barrier timed out";
+    case kDevBadPolicy: return "policy has an entry outside [0, m)";
+    default: return "unknown device error";
+  }
+}
+
+// Synchronises and copies the control block back; maps device errors.
+mbdp_status finish(void* ws, hipStream_t stream, Control* out) {
+  MBDP_HIP(hipMemcpyAsync(out, ws, sizeof(Control), hipMemcpyDeviceToHost, stream));
+  MBDP_HIP(hipStreamSynchronize(stream));
+  if (out->error)
+    return fail(MBDP_ERR_DEVICE, "device error %u: %s", out->error, device_error_text(out->error));
+  return MBDP_OK;
+}
+
+void fill_stats(const Control& c, bool with_ref, mbdp_stats* st) {
+  if (!st) return;
+  st->sweeps = c.sweeps;
+  st->outer_iters = c.outer_iters;
+  st->policy_changes_last = c.policy_changes_last;
+  st->recentrings = c.recentrings;
+  st->final_dv_inf = c.final_dv_inf;
+  st->final_err_ref = with_ref ? c.final_err_ref : NAN;
+  st->shift = c.shift;
+  st->converged = c.converged;
+  st->reserved = 0;
+}
+
+std::mutex g_inspect_mutex;
+
+}  // namespace
+
+namespace mbdp {
+int inspect_flags_ptr(void** out);  // mbdp_kernels.hip
+}
+
+extern "C" {
+
+const char* mbdp_last_error(void) { return g_err.c_str(); }
+
+mbdp_status mdp_create_dense(int64_t n, int32_t m, const float* P, const float* c, double gamma,
+                             mbdp_mdp_t* out) {
+  if (!out) return fail(MBDP_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || n >= kMaxStates) return fail(MBDP_ERR_INVALID_ARG, "n = %lld not in [1, 2^31)", (long long)n);
+  if (m < 1) return fail(MBDP_ERR_INVALID_ARG, "m = %d < 1", m);
+  if (m > kMaxDenseActions)
+    return fail(MBDP_ERR_UNSUPPORTED, "dense storage supports m <= %d (got %d)", kMaxDenseActions, m);
+  if (!P || !c) return fail(MBDP_ERR_INVALID_ARG, "P or c is NULL");
+  if (!gamma_ok(gamma)) return fail(MBDP_ERR_INVALID_ARG, "gamma = %g not in (0, 1)", gamma);
+  mbdp_mdp* h = new (std::nothrow) mbdp_mdp();
+  if (!h) return fail(MBDP_ERR_HIP, "out of host memory");
+  h->storage = kDense;
+  h->n = n;
+  h->m = m;
+  h->gamma = gamma;
+  h->P = P;
+  h->c = c;
+  const mbdp_status st = query_device(h);
+  if (st != MBDP_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return MBDP_OK;
+}
+
+mbdp_status mdp_create_csr(int64_t n, int32_t m, const int64_t* row_ptr, const int32_t* col,
+                           const float* val, int64_t nnz, const float* c, double gamma,
+                           hipStream_t stream, mbdp_mdp_t* out) {
+  if (!out) return fail(MBDP_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || n >= kMaxStates) return fail(MBDP_ERR_INVALID_ARG, "n = %lld not in [1, 2^31)", (long long)n);
+  if (m < 1) return fail(MBDP_ERR_INVALID_ARG, "m = %d < 1", m);
+  if (nnz < 0) return fail(MBDP_ERR_INVALID_ARG, "nnz = %lld < 0", (long long)nnz);
+  if (!row_ptr || !c || (nnz > 0 && (!col || !val)))
+    return fail(MBDP_ERR_INVALID_ARG, "row_ptr, col, val or c is NULL");
+  if (!gamma_ok(gamma)) return fail(MBDP_ERR_INVALID_ARG, "gamma = %g not in (0, 1)", gamma);
+  mbdp_mdp* h = new (std::nothrow) mbdp_mdp();
+  if (!h) return fail(MBDP_ERR_HIP, "out of host memory");
+  h->storage = kCsr;
+  h->n = n;
+  h->m = m;
+  h->gamma = gamma;
+  h->row_ptr = row_ptr;
+  h->col = col;
+  h->val = val;
+  h->nnz = nnz;
+  h->c = c;
+  mbdp_status st = query_device(h);
+  if (st != MBDP_OK) {
+    delete h;
+    return st;
+  }
+  // Inspect the structure on the device: constant row length, monotone
+  // row_ptr consistent with nnz, columns in range.
+  const int64_t rows = n * (int64_t)m;
+  const int64_t k = (nnz % rows == 0) ? nnz / rows : -1;
+  unsigned long long flags[8] = {0};
+  {
+    std::lock_guard<std::mutex> lock(g_inspect_mutex);
+    void* dflags = nullptr;
+    hipError_t e = (hipError_t)inspect_flags_ptr(&dflags);
+    if (e == hipSuccess && launch_zero(dflags, sizeof flags, stream) != 0) e = hipGetLastError();
+    if (e == hipSuccess &&
+        launch_csr_inspect(row_ptr, col, rows, n, nnz, k,
+                           static_cast<unsigned long long*>(dflags), stream) != 0)
+      e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(flags, dflags, sizeof flags, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      delete h;
+      return fail(MBDP_ERR_HIP, "CSR inspection failed: %s", hipGetErrorString(e));
+    }
+  }
+  if (flags[1] || flags[2]) {
+    delete h;
+    return fail(MBDP_ERR_INVALID_ARG, "row_ptr is not non-decreasing from 0 to nnz");
+  }
+  if (flags[3]) {
+    delete h;
+    return fail(MBDP_ERR_INVALID_ARG, "%llu column indices outside [0, n)", flags[3]);
+  }
+  if (flags[0] == 0 && k >= 4 && k <= 256 && k % 4 == 0) {
+    h->storage = kEll;
+    h->ell_k = (int32_t)k;
+  }
+  *out = h;
+  return MBDP_OK;
+}
+
+mbdp_status mdp_destroy(mbdp_mdp_t h) {
+  delete h;
+  return MBDP_OK;
+}
+
+mbdp_status mdp_set_tuning(mbdp_mdp_t h, const mbdp_tuning* t) {
+  if (!h || !t) return fail(MBDP_ERR_INVALID_ARG, "handle or tuning is NULL");
+  if (t->threads_per_block != 0 && t->threads_per_block != 256 && t->threads_per_block != 512 &&
+      t->threads_per_block != 1024)
+    return fail(MBDP_ERR_INVALID_ARG, "threads_per_block must be 0, 256, 512 or 1024");
+  if (t->blocks_per_cu < 0 || t->blocks_per_cu > kMaxBlocksPerCu)
+    return fail(MBDP_ERR_INVALID_ARG, "blocks_per_cu must be in [0, %d]", kMaxBlocksPerCu);
+  h->tuning = *t;
+  return MBDP_OK;
+}
+
+size_t mdp_workspace_bytes(mbdp_mdp_t h, int64_t b) {
+  if (!h || b < 1 || b > h->n) return 0;
+  return layout(h).total;
+}
+
+mbdp_status mdp_validate(mbdp_mdp_t h, double row_sum_tol, void* workspace, size_t ws_bytes,
+                         hipStream_t stream, mbdp_validation* report) {
+  if (!h) return fail(MBDP_ERR_INVALID_ARG, "handle is NULL");
+  if (!(row_sum_tol >= 0.0)) return fail(MBDP_ERR_INVALID_ARG, "row_sum_tol must be >= 0");
+  mbdp_status st = check_ws(h, workspace, ws_bytes);
+  if (st != MBDP_OK) return st;
+  KParams p = base_params(h, workspace, nullptr, 1);
+  unsigned long long* out = static_cast<unsigned long long*>(workspace);
+  unsigned long long res[8] = {0};
+  if (launch_zero(out, sizeof res, stream) != 0)
+    return fail(MBDP_ERR_HIP, "clear failed: %s", hipGetErrorString(hipGetLastError()));
+  if (launch_validate(p, row_sum_tol, out, stream) != 0)
+    return fail(MBDP_ERR_HIP, "validate launch failed: %s", hipGetErrorString(hipGetLastError()));
+  MBDP_HIP(hipMemcpyAsync(res, out, sizeof res, hipMemcpyDeviceToHost, stream));
+  MBDP_HIP(hipStreamSynchronize(stream));
+  mbdp_validation v;
+  v.bad_probability = (int64_t)res[0];
+  v.bad_row_sum = (int64_t)res[1];
+  v.empty_rows = (int64_t)res[2];
+  v.bad_column = (int64_t)res[3];
+  v.bad_row_ptr = (int64_t)res[4];
+  v.bad_cost = (int64_t)res[5];
+  v.no_admissible_action = (int64_t)res[6];
+  double dev;
+  memcpy(&dev, &res[7], sizeof dev);
+  v.max_row_sum_dev = dev;
+  if (report) *report = v;
+  if (v.bad_probability || v.bad_row_sum || v.empty_rows || v.bad_column || v.bad_row_ptr ||
+      v.bad_cost || v.no_admissible_action)
+    return fail(MBDP_ERR_VALIDATION,
+                "invalid MDP: %lld bad probabilities, %lld bad row sums (max dev %g), %lld empty "
+                "rows, %lld bad columns, %lld bad costs, %lld states without admissible action",
+                (long long)v.bad_probability, (long long)v.bad_row_sum, v.max_row_sum_dev,
+                (long long)v.empty_rows, (long long)v.bad_column, (long long)v.bad_cost,
+                (long long)v.no_admissible_action);
+  return MBDP_OK;
+}
+
+mbdp_status mbdp_permutation(int64_t n, uint64_t seed, uint64_t sweep_index, int32_t* out,
+                             hipStream_t stream) {
+  if (n < 1 || n >= kMaxStates) return fail(MBDP_ERR_INVALID_ARG, "n = %lld not in [1, 2^31)", (long long)n);
+  if (!out) return fail(MBDP_ERR_INVALID_ARG, "out is NULL");
+  if (launch_permutation(n, seed, sweep_index, out, stream) != 0)
+    return fail(MBDP_ERR_HIP, "permutation launch failed: %s", hipGetErrorString(hipGetLastError()));
+  return MBDP_OK;
+}
+
+mbdp_status mb_sweep(mbdp_mdp_t h, float* V, const int32_t* policy, int64_t b, uint64_t seed,
+                     uint64_t sweep_index, const int32_t* perm, int32_t* argmin_out,
+                     float* dv_out, void* workspace, size_t ws_bytes, hipStream_t stream) {
+  if (!h) return fail(MBDP_ERR_INVALID_ARG, "handle is NULL");
+  if (!V) return fail(MBDP_ERR_INVALID_ARG, "V is NULL");
+  if (b < 1 || b > h->n)
+    return fail(MBDP_ERR_INVALID_ARG, "batch size b = %lld not in [1, n = %lld]", (long long)b,
+                (long long)h->n);
+  mbdp_status st = check_ws(h, workspace, ws_bytes);
+  if (st != MBDP_OK) return st;
+  KParams p = base_params(h, workspace, V, b);
+  p.task = kTaskSweep;
+  p.policy = const_cast<int32_t*>(policy);
+  p.policy_sweep = policy != nullptr;
+  p.perm = perm;
+  p.argmin_out = argmin_out;
+  p.seed = seed;
+  p.first_sweep = sweep_index;
+  st = launch(h, p, workspace, stream);
+  if (st != MBDP_OK) return st;
+  if (dv_out)
+    MBDP_HIP(hipMemcpyAsync(dv_out, &p.ctl->dv_last, sizeof(float), hipMemcpyDeviceToDevice, stream));
+  return MBDP_OK;
+}
+
+mbdp_status mbdp_sync_status(void* workspace, size_t ws_bytes, hipStream_t stream) {
+  if (!workspace || ws_bytes < sizeof(Control))
+    return fail(MBDP_ERR_WORKSPACE, "workspace missing or too small");
+  Control c;
+  return finish(workspace, stream, &c);
+}
+
+mbdp_status vi_solve(mbdp_mdp_t h, float* V, int32_t* policy_out, int64_t b, uint64_t seed,
+                     uint64_t first_sweep, double tol_dv, double eps, const double* V_ref,
+                     int64_t max_sweeps, void* workspace, size_t ws_bytes, hipStream_t stream,
+                     mbdp_stats* stats) {
+  if (!h) return fail(MBDP_ERR_INVALID_ARG, "handle is NULL");
+  if (!V) return fail(MBDP_ERR_INVALID_ARG, "V is NULL");
+  if (b < 1 || b > h->n)
+    return fail(MBDP_ERR_INVALID_ARG, "batch size b = %lld not in [1, n = %lld]", (long long)b,
+                (long long)h->n);
+  if (max_sweeps < 1) return fail(MBDP_ERR_INVALID_ARG, "max_sweeps must be >= 1");
+  if (isnan(tol_dv)) return fail(MBDP_ERR_INVALID_ARG, "tol_dv is NaN");
+  if (V_ref && !(eps >= 0.0)) return fail(MBDP_ERR_INVALID_ARG, "eps must be >= 0 with V_ref");
+  mbdp_status st = check_ws(h, workspace, ws_bytes);
+  if (st != MBDP_OK) return st;
+  const WsLayout w = layout(h);
+  KParams p = base_params(h, workspace, V, b);
+  p.task = kTaskVI;
+  p.policy = policy_out;
+  p.want_policy_out = policy_out != nullptr;
+  p.seed = seed;
+  p.first_sweep = first_sweep;
+  p.tol_dv = tol_dv;
+  p.eps = eps;
+  p.vref = V_ref;
+  p.max_sweeps = max_sweeps;
+  p.recentre_every = recentre_interval(h);
+  if (p.recentre_every > 0) {
+    p.ceff = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.ceff);
+    p.rho = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.rho);
+  }
+  st = launch(h, p, workspace, stream);
+  if (st != MBDP_OK) return st;
+  Control c;
+  st = finish(workspace, stream, &c);
+  if (st != MBDP_OK) return st;
+  fill_stats(c, V_ref != nullptr, stats);
+  if (!c.converged)
+    return fail(MBDP_ERR_NOT_CONVERGED, "no stopping rule fired within %lld sweeps",
+                (long long)max_sweeps);
+  return MBDP_OK;
+}
+
+mbdp_status mpi_solve(mbdp_mdp_t h, float* V, int32_t* policy, int32_t policy_is_init, int32_t K,
+                      int64_t b, uint64_t seed, uint64_t first_sweep, double tol_dv, double eps,
+                      const double* V_ref, int64_t max_outer, void* workspace, size_t ws_bytes,
+                      hipStream_t stream, mbdp_stats* stats) {
+  if (!h) return fail(MBDP_ERR_INVALID_ARG, "handle is NULL");
+  if (!V || !policy) return fail(MBDP_ERR_INVALID_ARG, "V or policy is NULL");
+  if (K < 1) return fail(MBDP_ERR_INVALID_ARG, "K = %d < 1", K);
+  if (b < 1 || b > h->n)
+    return fail(MBDP_ERR_INVALID_ARG, "batch size b = %lld not in [1, n = %lld]", (long long)b,
+                (long long)h->n);
+  if (max_outer < 1) return fail(MBDP_ERR_INVALID_ARG, "max_outer must be >= 1");
+  if (isnan(tol_dv)) return fail(MBDP_ERR_INVALID_ARG, "tol_dv is NaN");
+  if (V_ref && !(eps >= 0.0)) return fail(MBDP_ERR_INVALID_ARG, "eps must be >= 0 with V_ref");
+  mbdp_status st = check_ws(h, workspace, ws_bytes);
+  if (st != MBDP_OK) return st;
+  const WsLayout w = layout(h);
+  KParams p = base_params(h, workspace, V, b);
+  p.task = kTaskMPI;
+  p.policy = policy;
+  p.policy_is_init = policy_is_init != 0;
+  p.K = K;
+  p.seed = seed;
+  p.first_sweep = first_sweep;
+  p.tol_dv = tol_dv;
+  p.eps = eps;
+  p.vref = V_ref;
+  p.max_outer = max_outer;
+  p.recentre_every = recentre_interval(h);
+  if (p.recentre_every > 0) {
+    p.ceff = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.ceff);
+    p.rho = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.rho);
+  }
+  st = launch(h, p, workspace, stream);
+  if (st != MBDP_OK) return st;
+  Control c;
+  st = finish(workspace, stream, &c);
+  if (st != MBDP_OK) return st;
+  fill_stats(c, V_ref != nullptr, stats);
+  if (!c.converged)
+    return fail(MBDP_ERR_NOT_CONVERGED, "no stopping rule fired within %lld outer iterations",
+                (long long)max_outer);
+  return MBDP_OK;
+}
+
+}  // extern "C"

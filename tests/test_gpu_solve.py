@@ -1,0 +1,177 @@
+"""GPU parity of the drivers (vi_solve, mpi_solve) against the oracle:
+the limit J* (policy iteration on the stored MDP), the greedy policy (up to
+near-ties), the first sweep that crosses eps in measurement mode, resuming
+at a sweep index, and MPI's stopping rule."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2110_02901_amd import binding as mb
+from paper_2110_02901_amd import inputs
+
+from gpu_util import check_argmin, csr_case, dense_case, dev, up
+
+pytestmark = pytest.mark.gpu
+
+
+def zeros(n, dtype=torch.float32):
+    return torch.zeros(n, dtype=dtype, device=dev())
+
+
+def assert_optimal_policy(mdp, Vstar, pol, tol):
+    Q = oracle.q_values(mdp, np.arange(mdp.n), Vstar)
+    check_argmin(Q, pol, tol)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    # 64 states, 4 actions, Dirichlet(1) rows drawn in FP64, stored FP32
+    P64, c64 = inputs.dense_mdp(64, 4, 1.0, 1, dtype=np.float64)
+    P, c = P64.astype(np.float32), c64.astype(np.float32)
+    h, mdp = dense_case(P, c, 0.9)
+    Vstar, mustar, _ = oracle.policy_iteration(mdp)
+    return h, mdp, Vstar
+
+
+def test_vi_64x4_to_tolerance(c1):
+    h, mdp, Vstar = c1
+    ws = mb.workspace(h, 16)
+    V = zeros(64)
+    pol = torch.zeros(64, dtype=torch.int32, device=dev())
+    st = mb.vi_solve(h, V, 16, 101, ws, tol_dv=1e-8, max_sweeps=5000, policy_out=pol)
+    assert st["converged"] and st["final_dv_inf"] <= 1e-8
+    Vg = V.cpu().numpy()
+    assert np.max(np.abs(Vg - Vstar)) <= 1e-6
+    assert_optimal_policy(mdp, Vstar, pol.cpu().numpy(), 1e-5 * np.max(np.abs(Vstar)))
+    # the oracle takes a comparable number of sweeps under the same orders
+    _, _, ost = oracle.value_iteration(mdp, 16, 101, tol_dv=1e-8, max_sweeps=5000)
+    assert abs(st["sweeps"] - ost.sweeps) <= max(3, 0.05 * ost.sweeps)
+
+
+@pytest.mark.parametrize("b", [1, 16, 64])
+def test_vi_first_crossing_matches_oracle(c1, b):
+    h, mdp, Vstar = c1
+    ws = mb.workspace(h, b)
+    V = zeros(64)
+    st = mb.vi_solve(h, V, b, 101, ws, tol_dv=-1.0, eps=1e-6, V_ref=up(Vstar), max_sweeps=5000)
+    _, _, ost = oracle.value_iteration(mdp, b, 101, tol_dv=-1, V_ref=Vstar, eps=1e-6)
+    assert st["converged"] and st["final_err_ref"] <= 1e-6
+    assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= 1e-6 + 1e-12
+    assert abs(st["sweeps"] - ost.sweeps) <= 2, (st["sweeps"], ost.sweeps)
+
+
+def test_vi_resume_reproduces_uninterrupted_run(c1):
+    h, mdp, _ = c1
+    mb.mdp_set_tuning(h, recentre_every=-1)
+    try:
+        ws = mb.workspace(h, 16)
+        full = zeros(64)
+        mb.vi_solve(h, full, 16, 7, ws, max_sweeps=20)
+        part = zeros(64)
+        mb.vi_solve(h, part, 16, 7, ws, max_sweeps=12)
+        mb.vi_solve(h, part, 16, 7, ws, first_sweep=12, max_sweeps=8)
+        assert torch.equal(full, part)
+    finally:
+        mb.mdp_set_tuning(h)
+
+
+def test_vi_not_converged_is_soft(c1):
+    h, _, _ = c1
+    ws = mb.workspace(h, 16)
+    V = zeros(64)
+    st = mb.vi_solve(h, V, 16, 1, ws, tol_dv=0.0, max_sweeps=3)
+    assert not st["converged"] and st["sweeps"] == 3
+
+
+@pytest.mark.parametrize("K,b,init", [(5, 16, False), (1, 64, False), (5, 1, True)])
+def test_mpi_64x4(c1, K, b, init):
+    h, mdp, Vstar = c1
+    ws = mb.workspace(h, b)
+    V = zeros(64)
+    pol = up(inputs.policy(64, 4, 3)) if init else torch.zeros(64, dtype=torch.int32, device=dev())
+    st = mb.mpi_solve(h, V, pol, K, b, 101, ws, policy_is_init=init, tol_dv=1e-7,
+                      max_outer=2000)
+    assert st["converged"] and st["policy_changes_last"] == 0
+    assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= 2e-6
+    assert_optimal_policy(mdp, Vstar, pol.cpu().numpy(), 1e-5 * np.max(np.abs(Vstar)))
+
+
+def test_mpi_first_crossing_matches_oracle(c1):
+    h, mdp, Vstar = c1
+    ws = mb.workspace(h, 16)
+    V = zeros(64)
+    pol = torch.zeros(64, dtype=torch.int32, device=dev())
+    st = mb.mpi_solve(h, V, pol, 5, 16, 101, ws, policy_is_init=False, tol_dv=-1.0, eps=1e-6,
+                      V_ref=up(Vstar), max_outer=2000)
+    _, _, ost = oracle.modified_policy_iteration(mdp, 5, 16, 101, tol_dv=-1, V_ref=Vstar,
+                                                 eps=1e-6)
+    assert st["converged"] and abs(st["sweeps"] - ost.sweeps) <= 2, (st, ost)
+
+
+@pytest.fixture(scope="module")
+def dense_1024():
+    P, c = inputs.dense_mdp(1024, 16, 0.1, 2, dtype=np.float32)
+    h, mdp = dense_case(P, c, 0.99)
+    Vstar, _, _ = oracle.policy_iteration(mdp)
+    return h, mdp, Vstar
+
+
+@pytest.mark.parametrize("b", [1024, 128, 32])
+def test_vi_dense_1024x16_reaches_eps(dense_1024, b):
+    """gamma = 0.99 and V* ~ 6: eps = 1e-6 needs the re-centred iterate."""
+    h, mdp, Vstar = dense_1024
+    ws = mb.workspace(h, b)
+    V = zeros(1024)
+    pol = torch.zeros(1024, dtype=torch.int32, device=dev())
+    st = mb.vi_solve(h, V, b, 102, ws, tol_dv=-1.0, eps=1e-6, V_ref=up(Vstar),
+                     max_sweeps=4000, policy_out=pol)
+    assert st["converged"], st
+    assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= 1e-6 + 1e-7
+    assert st["recentrings"] >= 1
+    assert_optimal_policy(mdp, Vstar, pol.cpu().numpy(), 1e-5 * np.max(np.abs(Vstar)))
+
+
+def test_mpi_dense_1024x16_reaches_eps(dense_1024):
+    h, mdp, Vstar = dense_1024
+    ws = mb.workspace(h, 128)
+    V = zeros(1024)
+    pol = torch.zeros(1024, dtype=torch.int32, device=dev())
+    st = mb.mpi_solve(h, V, pol, 5, 128, 102, ws, policy_is_init=False, tol_dv=-1.0, eps=1e-6,
+                      V_ref=up(Vstar), max_outer=2000)
+    assert st["converged"], st
+    assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= 1e-6 + 1e-7
+
+
+@pytest.mark.parametrize("band", [64, None])
+def test_vi_and_mpi_sparse_reach_eps(band):
+    n, m, k = 3000, 8, 32
+    rp, col, val, c = inputs.csr_mdp(n, m, k, 1.0, 3, band=band)
+    h, mdp = csr_case(rp, col, val, c, 0.995)
+    Vstar, _, _ = oracle.policy_iteration(mdp)
+    for b in (3000, 300):
+        ws = mb.workspace(h, b)
+        V = zeros(n)
+        pol = torch.zeros(n, dtype=torch.int32, device=dev())
+        st = mb.vi_solve(h, V, b, 103, ws, tol_dv=-1.0, eps=1e-6, V_ref=up(Vstar),
+                         max_sweeps=20000, policy_out=pol)
+        assert st["converged"], st
+        assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= 1e-6 + 1e-7
+        assert_optimal_policy(mdp, Vstar, pol.cpu().numpy(), 1e-5 * np.max(np.abs(Vstar)))
+    ws = mb.workspace(h, 300)
+    V = zeros(n)
+    pol = torch.zeros(n, dtype=torch.int32, device=dev())
+    st = mb.mpi_solve(h, V, pol, 5, 300, 103, ws, policy_is_init=False, tol_dv=-1.0, eps=1e-6,
+                      V_ref=up(Vstar), max_outer=20000)
+    assert st["converged"], st
+
+
+def test_general_csr_vi():
+    n, m = 500, 3
+    rp, col, val, c = inputs.csr_ragged_mdp(n, m, 1, 12, 1.0, 80)
+    h, mdp = csr_case(rp, col, val, c, 0.95)
+    Vstar, _, _ = oracle.policy_iteration(mdp)
+    ws = mb.workspace(h, 50)
+    V = zeros(n)
+    st = mb.vi_solve(h, V, 50, 3, ws, tol_dv=-1.0, eps=1e-6, V_ref=up(Vstar), max_sweeps=5000)
+    assert st["converged"] and np.max(np.abs(V.cpu().numpy() - Vstar)) <= 1.1e-6
