@@ -142,15 +142,22 @@ __device__ __forceinline__ void atomic_store_agent(unsigned long long* p, unsign
 
 // ------------------------------------------------------------ grid barrier
 //
-// All workgroups of a cooperative launch meet here.  Every thread makes its
-// global writes visible device-wide (agent-scope release), one thread per
-// workgroup increments the monotone arrival counter and waits until all
-// workgroups of this barrier arrived, then acquires.  The wait gives up
-// after `timeout` wall-clock ticks or when another workgroup raised the
-// abort flag, so no wave can spin forever.  Returns false when aborted.
+// All workgroups of a cooperative launch meet here, once per batch.  The
+// cost of a device-wide barrier on MI355X grows with the number of
+// workgroups and with contention on one atomic counter, so arrival is
+// contention-free: every wave first waits for its own memory operations
+// (vmcnt(0)), then one thread per workgroup makes the workgroup's writes
+// visible device-wide (agent-scope release: L2 write-back) and stores the
+// barrier generation into the workgroup's own arrival slot.  Workgroup 0
+// polls all slots in parallel (one per thread) and then publishes the
+// generation in a single release word that the others poll, followed by an
+// agent-scope acquire (L2 invalidate) before anyone reads shared data.
+// Every wait gives up after `timeout` wall-clock ticks or when another
+// workgroup raised the abort flag, so no wave can spin forever.  Returns
+// false when aborted.
 struct GridBarrier {
   Control* ctl;
-  unsigned long long target;
+  unsigned long long gen;      // barriers passed so far
   unsigned long long nblocks;
   unsigned long long timeout;
 };
@@ -160,31 +167,43 @@ __device__ __forceinline__ void raise_abort(Control* ctl, unsigned int code) {
   __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Spins until *word >= target; false on abort or timeout.
+__device__ __forceinline__ bool wait_at_least(const unsigned long long* word,
+                                              unsigned long long target, const GridBarrier& g) {
+  const unsigned long long t0 = wall_clock64();
+  while (atomic_load_agent(word) < target) {
+    if (__hip_atomic_load(&g.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    if (wall_clock64() - t0 > g.timeout) {
+      raise_abort(g.ctl, kDevBarrierTimeout);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
 __device__ __forceinline__ bool grid_sync(GridBarrier& g) {
   __shared__ int s_abort;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's loads and stores are done
   __syncthreads();
-  g.target += g.nblocks;
+  g.gen += 1;
+  unsigned long long* slots = g.ctl->bar_slots;
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(&g.ctl->bar_count, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long t0 = wall_clock64();
-    int aborted = 0;
-    while (atomic_load_agent(&g.ctl->bar_count) < g.target) {
-      if (__hip_atomic_load(&g.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        aborted = 1;
-        break;
-      }
-      if (wall_clock64() - t0 > g.timeout) {
-        raise_abort(g.ctl, kDevBarrierTimeout);
-        aborted = 1;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    atomic_store_agent(&slots[blockIdx.x], g.gen);
+  }
+  int ok = 1;
+  if (blockIdx.x == 0) {
+    for (unsigned i = threadIdx.x; i < g.nblocks && ok; i += blockDim.x)
+      ok = wait_at_least(&slots[i], g.gen, g);
+    __syncthreads();
+    if (threadIdx.x == 0) atomic_store_agent(&g.ctl->bar_release, g.gen);
+  }
+  if (threadIdx.x == 0) {
+    if (ok) ok = wait_at_least(&g.ctl->bar_release, g.gen, g);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (!aborted)
-      aborted = __hip_atomic_load(&g.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-    s_abort = aborted;
+    if (ok) ok = __hip_atomic_load(&g.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    s_abort = !ok;
   }
   __syncthreads();
   return s_abort == 0;

@@ -31,8 +31,10 @@ enum Acc : int {
   kNumAcc = 6
 };
 
+constexpr int kMaxBlocks = 4096;  // persistent workgroups per launch (arrival slots)
+
 struct alignas(256) Control {
-  unsigned long long bar_count;  // grid barrier arrivals (monotone)
+  unsigned long long bar_release;  // last barrier generation released by workgroup 0
   unsigned long long pad0[31];
   unsigned int abort;            // nonzero: every workgroup leaves
   unsigned int error;            // DeviceError
@@ -49,6 +51,7 @@ struct alignas(256) Control {
   int converged;
   int pad2;
   float dv_last;                 // last sweep's max |dV| as FP32 (mb_sweep)
+  unsigned long long bar_slots[kMaxBlocks] __attribute__((aligned(256)));  // arrival generations
 };
 
 struct KParams {

@@ -573,7 +573,7 @@ struct Driver {
 
   __device__ __forceinline__ explicit Driver(const KParams& kp) : p(kp) {
     g.ctl = p.ctl;
-    g.target = 0;
+    g.gen = 0;
     g.nblocks = gridDim.x;
     g.timeout = p.timeout_ticks;
     L.reset();
@@ -934,7 +934,8 @@ int launch_solve(KParams p, LaunchShape shape, void* stream, char* err, size_t e
     return -1;
   }
   const int bpc = shape.blocks_per_cu < occ ? shape.blocks_per_cu : occ;
-  const int blocks = shape.cus * bpc;
+  int blocks = shape.cus * bpc;
+  if (blocks > kMaxBlocks) blocks = kMaxBlocks;
   // dense: split the columns of a state over several workgroups when the
   // batch has fewer states than there are workgroups
   p.splits = 1;

@@ -94,8 +94,10 @@ mbdp_status check_ws(const mbdp_mdp* h, void* ws, size_t bytes) {
 LaunchShape shape_of(const mbdp_mdp* h) {
   LaunchShape s;
   s.cus = h->cus;
-  s.threads = h->storage == kDense ? 512 : 256;
-  s.blocks_per_cu = h->storage == kDense ? 2 : 8;
+  // One 1024-thread workgroup per CU: the grid barrier's cost grows with
+  // the number of workgroups, and 16 waves per CU keep enough loads in flight.
+  s.threads = 1024;
+  s.blocks_per_cu = 1;
   if (h->tuning.threads_per_block == 256 || h->tuning.threads_per_block == 512 ||
       h->tuning.threads_per_block == 1024)
     s.threads = h->tuning.threads_per_block;

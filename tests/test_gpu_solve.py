@@ -15,6 +15,12 @@ from gpu_util import check_argmin, csr_case, dense_case, dev, up
 pytestmark = pytest.mark.gpu
 
 
+def out_tol(eps, Vstar):
+    """eps plus half an FP32 ulp: the solve stops on the FP64 value W + r,
+    and the returned V is that value rounded to FP32."""
+    return eps + 0.5 * float(np.spacing(np.float32(np.max(np.abs(Vstar)))))
+
+
 def zeros(n, dtype=torch.float32):
     return torch.zeros(n, dtype=dtype, device=dev())
 
@@ -42,11 +48,12 @@ def test_vi_64x4_to_tolerance(c1):
     st = mb.vi_solve(h, V, 16, 101, ws, tol_dv=1e-8, max_sweeps=5000, policy_out=pol)
     assert st["converged"] and st["final_dv_inf"] <= 1e-8
     Vg = V.cpu().numpy()
-    assert np.max(np.abs(Vg - Vstar)) <= 1e-6
+    assert np.max(np.abs(Vg - Vstar)) <= out_tol(1e-6, Vstar)
     assert_optimal_policy(mdp, Vstar, pol.cpu().numpy(), 1e-5 * np.max(np.abs(Vstar)))
-    # the oracle takes a comparable number of sweeps under the same orders
+    # The FP32 iterate's changes are multiples of ulp(W), so the dV rule
+    # fires at or somewhat after the oracle's FP64 crossing, never before.
     _, _, ost = oracle.value_iteration(mdp, 16, 101, tol_dv=1e-8, max_sweeps=5000)
-    assert abs(st["sweeps"] - ost.sweeps) <= max(3, 0.05 * ost.sweeps)
+    assert ost.sweeps - 2 <= st["sweeps"] <= 1.5 * ost.sweeps + 10, (st["sweeps"], ost.sweeps)
 
 
 @pytest.mark.parametrize("b", [1, 16, 64])
@@ -57,7 +64,7 @@ def test_vi_first_crossing_matches_oracle(c1, b):
     st = mb.vi_solve(h, V, b, 101, ws, tol_dv=-1.0, eps=1e-6, V_ref=up(Vstar), max_sweeps=5000)
     _, _, ost = oracle.value_iteration(mdp, b, 101, tol_dv=-1, V_ref=Vstar, eps=1e-6)
     assert st["converged"] and st["final_err_ref"] <= 1e-6
-    assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= 1e-6 + 1e-12
+    assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= out_tol(1e-6, Vstar)
     assert abs(st["sweeps"] - ost.sweeps) <= 2, (st["sweeps"], ost.sweeps)
 
 
@@ -93,7 +100,7 @@ def test_mpi_64x4(c1, K, b, init):
     st = mb.mpi_solve(h, V, pol, K, b, 101, ws, policy_is_init=init, tol_dv=1e-7,
                       max_outer=2000)
     assert st["converged"] and st["policy_changes_last"] == 0
-    assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= 2e-6
+    assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= out_tol(1e-6, Vstar)
     assert_optimal_policy(mdp, Vstar, pol.cpu().numpy(), 1e-5 * np.max(np.abs(Vstar)))
 
 
@@ -127,7 +134,7 @@ def test_vi_dense_1024x16_reaches_eps(dense_1024, b):
     st = mb.vi_solve(h, V, b, 102, ws, tol_dv=-1.0, eps=1e-6, V_ref=up(Vstar),
                      max_sweeps=4000, policy_out=pol)
     assert st["converged"], st
-    assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= 1e-6 + 1e-7
+    assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= out_tol(1e-6, Vstar)
     assert st["recentrings"] >= 1
     assert_optimal_policy(mdp, Vstar, pol.cpu().numpy(), 1e-5 * np.max(np.abs(Vstar)))
 
@@ -140,7 +147,7 @@ def test_mpi_dense_1024x16_reaches_eps(dense_1024):
     st = mb.mpi_solve(h, V, pol, 5, 128, 102, ws, policy_is_init=False, tol_dv=-1.0, eps=1e-6,
                       V_ref=up(Vstar), max_outer=2000)
     assert st["converged"], st
-    assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= 1e-6 + 1e-7
+    assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= out_tol(1e-6, Vstar)
 
 
 @pytest.mark.parametrize("band", [64, None])
@@ -156,7 +163,7 @@ def test_vi_and_mpi_sparse_reach_eps(band):
         st = mb.vi_solve(h, V, b, 103, ws, tol_dv=-1.0, eps=1e-6, V_ref=up(Vstar),
                          max_sweeps=20000, policy_out=pol)
         assert st["converged"], st
-        assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= 1e-6 + 1e-7
+        assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= out_tol(1e-6, Vstar)
         assert_optimal_policy(mdp, Vstar, pol.cpu().numpy(), 1e-5 * np.max(np.abs(Vstar)))
     ws = mb.workspace(h, 300)
     V = zeros(n)
@@ -174,4 +181,4 @@ def test_general_csr_vi():
     ws = mb.workspace(h, 50)
     V = zeros(n)
     st = mb.vi_solve(h, V, 50, 3, ws, tol_dv=-1.0, eps=1e-6, V_ref=up(Vstar), max_sweeps=5000)
-    assert st["converged"] and np.max(np.abs(V.cpu().numpy() - Vstar)) <= 1.1e-6
+    assert st["converged"] and np.max(np.abs(V.cpu().numpy() - Vstar)) <= out_tol(1e-6, Vstar)
