@@ -43,9 +43,10 @@ def library_hash():
     return h.hexdigest()[:16]
 
 
-def committed_traffic(workload, algo_bytes_per_launch):
-    """HBM traffic per launch from the committed rocprofv3 counter summary,
-    if it was taken with the current kernel sources; else None."""
+def committed_traffic(workload, sweeps_per_launch):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (sweeps x bytes per sweep + the one-off prologue), if the counters were
+    taken with the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % workload)
     if not os.path.exists(path):
         return None
@@ -58,10 +59,10 @@ def committed_traffic(workload, algo_bytes_per_launch):
         return None
     try:
         per_sweep = float(vals["hbm_bytes_per_sweep"])
-        algo_per_sweep = float(vals["algorithmic_bytes_per_sweep"])
+        prologue = float(vals["hbm_bytes_prologue"])
     except (KeyError, ValueError):
         return None
-    return per_sweep / algo_per_sweep * algo_bytes_per_launch
+    return sweeps_per_launch * per_sweep + prologue
 
 
 def cpu_baseline(P, c, gamma, b, seed, budget_s=20.0):
@@ -99,6 +100,11 @@ def main():
     ap.add_argument("--cpu-baseline-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mpi", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--profile-sweeps", type=int, default=0,
+                    help="only run one vi_solve of exactly this many sweeps at the first "
+                         "batch size (per-sweep counter measurement)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the mini-batch sweep is built and timed on a "
@@ -115,6 +121,16 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe:
+        # a plain copy kernel of known size: 1 GiB read + 1 GiB written per launch
+        x = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": x.numel() * 4,
+                          "copy_probe_bytes_written": y.numel() * 4, "launches": 3}))
+        return
     wl_name = "dense-8192x16"
     wl = inputs.WORKLOADS[wl_name]
     n, m, gamma = wl["n"], wl["m"], wl["gamma"]
@@ -129,6 +145,22 @@ def main():
     h = mb.mdp_create_dense(Pd, cd, gamma)
     ws = mb.workspace(h, n)
     stream = torch.cuda.current_stream()
+
+    if args.profile_sweeps:
+        b = batch_sizes[0]
+        V = torch.zeros(n, dtype=torch.float32, device=dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        st = mb.vi_solve(h, V, b, seed, ws, tol_dv=-1.0, max_sweeps=args.profile_sweeps)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        print(json.dumps({"profile_sweeps": st["sweeps"], "b": b, "ms": ms,
+                          "algorithmic_bytes": st["sweeps"] * n * m * (4 * n + 4),
+                          "algorithmic_bytes_per_sweep": n * m * (4 * n + 4),
+                          "library_hash": library_hash()}))
+        return
 
     # Reference V* for the time-to-eps rule: MPI run until the FP32 iterate
     # stops moving (its error against the FP64 optimum is checked by the
@@ -197,8 +229,7 @@ def main():
     backups = total_sweeps * n * m
     value = backups / wall
     kernel_gbps = backups * bytes_per_backup / total_s / 1e9
-    algo_per_launch = total_sweeps / args.steps * n * m * bytes_per_backup
-    traffic = committed_traffic(wl_name, algo_per_launch)
+    traffic = committed_traffic(wl_name, total_sweeps / args.steps)
 
     line = {
         "metric": METRIC,
