@@ -67,7 +67,6 @@ typedef struct {
   double final_dv_inf;         /* VI: max|V_{t+1} - V_t| of the last sweep;
                                   MPI: Bellman residual max|TV - V| of the last improvement */
   double final_err_ref;        /* max|V - V_ref| after the last sweep (NaN without V_ref) */
-  double shift;                /* final re-centring offset r (V = W + r) */
   int32_t converged;           /* 1 if a stopping rule fired before the limit */
   int32_t reserved;
 } mbdp_stats;
@@ -88,8 +87,9 @@ typedef struct {
 typedef struct {
   int32_t blocks_per_cu;       /* persistent workgroups per compute unit */
   int32_t threads_per_block;   /* 256, 512 or 1024 */
-  int32_t recentre_every;      /* solvers: sweeps between re-centrings; -1 disables */
-  int32_t reserved;
+  int32_t recentre_every;      /* solvers: minimum sweeps between re-centrings; -1 disables */
+  int32_t recentre_force;      /* nonzero: re-centre after every recentre_every sweeps
+                                  whatever the size of the change (testing) */
 } mbdp_tuning;
 
 /* Dense MDP (P as in Sec. II-A, stored [n][m][n]).  Records the pointers;
@@ -163,16 +163,22 @@ mbdp_status mbdp_sync_status(void* workspace, size_t ws_bytes, hipStream_t strea
  * order sigma_t until max|V_{t+1} - V_t| <= tol_dv (tol_dv < 0 disables),
  * or -- when V_ref (device FP64[n]) is given -- max|V_{t+1} - V_ref| <= eps,
  * or max_sweeps sweeps.  All sweeps run in one persistent kernel launch
- * with a device-wide barrier between batches.  The iterate is kept as
- * W = V - r with costs c - r + gamma*r*rowsum(P) (exact in real arithmetic)
- * and r re-centred every few sweeps, so FP32 resolves V to ~ulp(max|W|).
- * On return V holds the last iterate and, if policy_out (device int32[n])
- * is given, the greedy policy at V (lowest index on ties).  stats may be
+ * with a device-wide barrier between batches.
+ * Precision: the iterate is kept as V = W + R with W in FP32 and an FP64
+ * anchor R, iterating W with the costs c(s,a) - R(s) + gamma (P R)(s,a);
+ * this is exact in real arithmetic for any order and batch size.  Whenever
+ * a sweep changes W by less than 2^-14 of its magnitude, W is folded into R
+ * (one extra pass over P), so FP32 resolves the remaining error rather than
+ * |V|.  By the contraction property (Sec. III-B), max|V_{t+1} - V_t| <= tol
+ * implies max|V_{t+1} - J*| <= tol * gamma / (1 - gamma).
+ * On return V holds the last iterate in FP32, V64_out (device FP64[n], may
+ * be NULL) the same iterate W + R in FP64, and policy_out (device int32[n],
+ * may be NULL) the greedy policy at V (lowest index on ties).  stats may be
  * NULL.  Returns MBDP_ERR_NOT_CONVERGED when the limit was reached. */
-mbdp_status vi_solve(mbdp_mdp_t h, float* V, int32_t* policy_out, int64_t b, uint64_t seed,
-                     uint64_t first_sweep, double tol_dv, double eps, const double* V_ref,
-                     int64_t max_sweeps, void* workspace, size_t ws_bytes, hipStream_t stream,
-                     mbdp_stats* stats);
+mbdp_status vi_solve(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy_out, int64_t b,
+                     uint64_t seed, uint64_t first_sweep, double tol_dv, double eps,
+                     const double* V_ref, int64_t max_sweeps, void* workspace, size_t ws_bytes,
+                     hipStream_t stream, mbdp_stats* stats);
 
 /* MB-MPI: Algorithm 1 with its K policy-evaluation steps done by B_{mu,b}
  * (warm start from the current V).  policy (device int32[n]) is the initial
@@ -182,12 +188,14 @@ mbdp_status vi_solve(mbdp_mdp_t h, float* V, int32_t* policy_out, int64_t b, uin
  * and then the improvement step over all states (V fixed).  Stops when an
  * improvement changes no action and the Bellman residual max|TV - V| is
  * <= tol_dv, or -- with V_ref -- after the first evaluation sweep with
- * max|V - V_ref| <= eps, or after max_outer outer iterations.  On return V
- * and policy hold the last iterate. */
-mbdp_status mpi_solve(mbdp_mdp_t h, float* V, int32_t* policy, int32_t policy_is_init, int32_t K,
-                      int64_t b, uint64_t seed, uint64_t first_sweep, double tol_dv, double eps,
-                      const double* V_ref, int64_t max_outer, void* workspace, size_t ws_bytes,
-                      hipStream_t stream, mbdp_stats* stats);
+ * max|V - V_ref| <= eps, or after max_outer outer iterations.  Precision
+ * and V64_out as for vi_solve.  On return V and policy hold the last
+ * iterate. */
+mbdp_status mpi_solve(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy,
+                      int32_t policy_is_init, int32_t K, int64_t b, uint64_t seed,
+                      uint64_t first_sweep, double tol_dv, double eps, const double* V_ref,
+                      int64_t max_outer, void* workspace, size_t ws_bytes, hipStream_t stream,
+                      mbdp_stats* stats);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* mbdp_last_error(void);

@@ -356,13 +356,21 @@ def row_sums(mdp):
 
 
 def shifted_costs(mdp, r):
-    """Costs c' for iterating W = V - r*e instead of V.
+    """Costs c' for iterating W = V - r instead of V, r a scalar or a vector.
 
-    By the shift-invariance lemma (Sec. III-B.1), adding r to every entry of
-    V adds gamma*r*rho(s,a) inside each bracket of eq. (11) (rho = 1 for
-    stochastic rows).  With c'(s,a) = c(s,a) - r + gamma*r*rho(s,a) one
-    therefore has B'(V - r e) = B(V) - r e for any order and batch size,
-    where B' is the operator with costs c'.  Exact in real arithmetic.
+    Every value a state reads in eq. (11) -- old or new -- is V(j) = W(j) + r(j),
+    so each bracket c(s,a) + gamma * sum_j P(s,a,j) V(j) equals
+    [c(s,a) - r(s) + gamma * (P r)(s,a)] + r(s) + gamma * sum_j P(s,a,j) W(j).
+    With c'(s,a) = c(s,a) - r(s) + gamma * (P r)(s,a) the operator with costs
+    c' maps W to B(V) - r for any order and batch size (exact in real
+    arithmetic).  For a scalar r, P r = r * rho (the row sums), which is the
+    shift of the shift-invariance lemma (Sec. III-B.1) with rho = 1 for
+    stochastic rows.
     """
     c = np.asarray(mdp.c, dtype=np.float64)
-    return c - r + mdp.gamma * r * row_sums(mdp)
+    n = mdp.n
+    if np.ndim(r) == 0:
+        return c - r + mdp.gamma * r * row_sums(mdp)
+    r = np.asarray(r, dtype=np.float64)
+    Pr = _expected_values(mdp, np.arange(n), r, None)  # (P r)(s, a)
+    return c - r[:, None] + mdp.gamma * Pr

@@ -50,7 +50,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int64), ("outer_iters", ctypes.c_int64),
                 ("policy_changes_last", ctypes.c_int64), ("recentrings", ctypes.c_int64),
                 ("final_dv_inf", ctypes.c_double), ("final_err_ref", ctypes.c_double),
-                ("shift", ctypes.c_double), ("converged", ctypes.c_int32),
+                ("converged", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
@@ -69,7 +69,7 @@ class Validation(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_int32), ("threads_per_block", ctypes.c_int32),
-                ("recentre_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("recentre_every", ctypes.c_int32), ("recentre_force", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -87,9 +87,9 @@ _SIGS = {
     "mbdp_permutation": (_I32, [_I64, _U64, _U64, _P, _P]),
     "mb_sweep": (_I32, [_P, _P, _P, _I64, _U64, _U64, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "mbdp_sync_status": (_I32, [_P, ctypes.c_size_t, _P]),
-    "vi_solve": (_I32, [_P, _P, _P, _I64, _U64, _U64, _D, _D, _P, _I64, _P, ctypes.c_size_t,
-                        _P, ctypes.POINTER(Stats)]),
-    "mpi_solve": (_I32, [_P, _P, _P, _I32, _I32, _I64, _U64, _U64, _D, _D, _P, _I64, _P,
+    "vi_solve": (_I32, [_P, _P, _P, _P, _I64, _U64, _U64, _D, _D, _P, _I64, _P,
+                        ctypes.c_size_t, _P, ctypes.POINTER(Stats)]),
+    "mpi_solve": (_I32, [_P, _P, _P, _P, _I32, _I32, _I64, _U64, _U64, _D, _D, _P, _I64, _P,
                          ctypes.c_size_t, _P, ctypes.POINTER(Stats)]),
     "mbdp_last_error": (ctypes.c_char_p, []),
 }
@@ -196,8 +196,8 @@ def mdp_destroy(h):
     h.close()
 
 
-def mdp_set_tuning(h, blocks_per_cu=0, threads_per_block=0, recentre_every=0):
-    t = Tuning(blocks_per_cu, threads_per_block, recentre_every, 0)
+def mdp_set_tuning(h, blocks_per_cu=0, threads_per_block=0, recentre_every=0, recentre_force=0):
+    t = Tuning(blocks_per_cu, threads_per_block, recentre_every, int(bool(recentre_force)))
     _check(lib().mdp_set_tuning(h.ptr, ctypes.byref(t)))
 
 
@@ -254,7 +254,7 @@ def mbdp_sync_status(ws, stream=None):
 
 
 def vi_solve(h, V, b, seed, ws, first_sweep=0, tol_dv=-1.0, eps=0.0, V_ref=None,
-             max_sweeps=100000, policy_out=None, stream=None):
+             max_sweeps=100000, policy_out=None, V64_out=None, stream=None):
     """Returns the statistics dict (``converged`` False when the limit was hit)."""
     import torch
     _require(V, torch.float32, h.n, "V")
@@ -262,27 +262,32 @@ def vi_solve(h, V, b, seed, ws, first_sweep=0, tol_dv=-1.0, eps=0.0, V_ref=None,
         _require(V_ref, torch.float64, h.n, "V_ref")
     if policy_out is not None:
         _require(policy_out, torch.int32, h.n, "policy_out")
+    if V64_out is not None:
+        _require(V64_out, torch.float64, h.n, "V64_out")
     st = Stats()
-    status = lib().vi_solve(h.ptr, _ptr(V), _ptr(policy_out), int(b), int(seed), int(first_sweep),
-                            float(tol_dv), float(eps), _ptr(V_ref), int(max_sweeps), _ptr(ws),
-                            ws.numel(), _stream(stream), ctypes.byref(st))
+    status = lib().vi_solve(h.ptr, _ptr(V), _ptr(V64_out), _ptr(policy_out), int(b), int(seed),
+                            int(first_sweep), float(tol_dv), float(eps), _ptr(V_ref),
+                            int(max_sweeps), _ptr(ws), ws.numel(), _stream(stream),
+                            ctypes.byref(st))
     if status != MBDP_ERR_NOT_CONVERGED:
         _check(status)
     return st.as_dict()
 
 
 def mpi_solve(h, V, policy, K, b, seed, ws, policy_is_init=True, first_sweep=0, tol_dv=-1.0,
-              eps=0.0, V_ref=None, max_outer=10000, stream=None):
+              eps=0.0, V_ref=None, max_outer=10000, V64_out=None, stream=None):
     import torch
     _require(V, torch.float32, h.n, "V")
     _require(policy, torch.int32, h.n, "policy")
     if V_ref is not None:
         _require(V_ref, torch.float64, h.n, "V_ref")
+    if V64_out is not None:
+        _require(V64_out, torch.float64, h.n, "V64_out")
     st = Stats()
-    status = lib().mpi_solve(h.ptr, _ptr(V), _ptr(policy), int(bool(policy_is_init)), int(K),
-                             int(b), int(seed), int(first_sweep), float(tol_dv), float(eps),
-                             _ptr(V_ref), int(max_outer), _ptr(ws), ws.numel(), _stream(stream),
-                             ctypes.byref(st))
+    status = lib().mpi_solve(h.ptr, _ptr(V), _ptr(V64_out), _ptr(policy), int(bool(policy_is_init)),
+                             int(K), int(b), int(seed), int(first_sweep), float(tol_dv),
+                             float(eps), _ptr(V_ref), int(max_outer), _ptr(ws), ws.numel(),
+                             _stream(stream), ctypes.byref(st))
     if status != MBDP_ERR_NOT_CONVERGED:
         _check(status)
     return st.as_dict()

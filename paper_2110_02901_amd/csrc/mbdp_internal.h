@@ -47,7 +47,6 @@ struct alignas(256) Control {
   long long recentrings;
   double final_dv_inf;
   double final_err_ref;
-  double shift;
   int converged;
   int pad2;
   float dv_last;                 // last sweep's max |dV| as FP32 (mb_sweep)
@@ -68,7 +67,8 @@ struct KParams {
   int32_t pad0;
   const float* c32;        // plain costs [n*m]
   double* ceff;            // shifted costs [n*m] (solvers), workspace
-  double* rho;             // row sums [n*m] (solvers), workspace
+  double* shift;           // FP64 anchor R[n] with V = W + R (solvers), workspace
+  double* v64_out;         // optional FP64 copy of the final V
   // vectors
   float* vbuf0;            // caller's V
   float* vbuf1;            // ping-pong partner, workspace
@@ -86,8 +86,10 @@ struct KParams {
   int64_t max_outer;       // MPI
   int32_t K;               // MPI evaluation sweeps
   int32_t policy_is_init;  // MPI
-  int32_t recentre_every;  // 0: plain costs, no shift
+  int32_t recentre_every;  // 0: plain costs, no anchor; else min sweeps between re-centrings
   int32_t want_policy_out; // VI: greedy policy at the end into `policy`
+  int32_t recentre_force;  // re-centre after every sweep (respecting recentre_every)
+  int32_t pad2;
   double tol_dv;
   double eps;
   // decomposition
@@ -96,6 +98,7 @@ struct KParams {
   // workspace
   Control* ctl;
   int32_t* order;          // [3][n] sweep orders, by sweep index mod 3
+  uint32_t* first_mark;    // [2][n] stamp (t + 1) of the states in batch 0 of sweep t, by t % 2 (cleared per launch)
   float* partial;          // dense split partial sums
   unsigned int* unit_count;// dense split arrival counters
   unsigned long long timeout_ticks;
@@ -103,7 +106,7 @@ struct KParams {
 
 // Workspace layout, shared by the size query and the launches.
 struct WsLayout {
-  size_t ctl, unit_count, partial, order, vbuf1, ceff, rho, total;
+  size_t ctl, unit_count, partial, order, first_mark, vbuf1, ceff, shift, total;
   size_t zero_bytes;  // prefix cleared before every launch (control + counters)
 };
 
@@ -114,16 +117,18 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 inline WsLayout ws_layout(int32_t storage, int64_t n, int32_t m, int64_t max_units) {
   WsLayout w{};
   size_t off = 0;
+  // cleared before every launch: control block, split counters, first-batch stamps
   w.ctl = off;        off = align_up(off + sizeof(Control), 256);
   w.unit_count = off;
   if (storage == kDense) off = align_up(off + (size_t)max_units * sizeof(unsigned int), 256);
+  w.first_mark = off; off = align_up(off + 2 * (size_t)n * sizeof(uint32_t), 256);
   w.zero_bytes = off;
   w.partial = off;
   if (storage == kDense) off = align_up(off + (size_t)max_units * (size_t)m * sizeof(float), 256);
   w.order = off;      off = align_up(off + 3 * (size_t)n * sizeof(int32_t), 256);
   w.vbuf1 = off;      off = align_up(off + (size_t)n * sizeof(float), 256);
   w.ceff = off;       off = align_up(off + (size_t)n * (size_t)m * sizeof(double), 256);
-  w.rho = off;        off = align_up(off + (size_t)n * (size_t)m * sizeof(double), 256);
+  w.shift = off;      off = align_up(off + (size_t)n * sizeof(double), 256);
   w.total = off;
   return w;
 }

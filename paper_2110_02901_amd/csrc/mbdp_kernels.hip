@@ -14,7 +14,13 @@
 // other buffer W the new values of batch k and a copy of batch k-1 (still
 // missing there).  After the barrier the roles swap.  No state of a batch
 // can therefore read a value of its own batch (Jacobi inside a batch, as
-// eq. (11) requires: M_b(i) holds only earlier batches).
+// eq. (11) requires: M_b(i) holds only earlier batches).  Batches of one
+// sweep are disjoint, but the first batch of sweep t+1 may share states with
+// the last batch of sweep t (all of them when b = n); such states are
+// stamped when the first batch's order is drawn and not copied forward, so
+// the copy can never overwrite their new value.  Stamps live in two arrays
+// by sweep parity: with b = n the next sweep's stamps are written in the
+// same phase that reads the current sweep's.
 //
 // The hot loop is the row gather + dot product Q(s,a) = c(s,a) +
 // gamma * sum_s' P(s,a,s') V(s'):
@@ -113,34 +119,34 @@ __device__ __forceinline__ double slot_double(Control* ctl, int slot, int i) {
 // ------------------------------------------------------------ per-state commit
 
 struct Ctx {
-  float* rd;   // read buffer: V before the current batch (complete)
+  float* rd;   // read buffer: W before the current batch (complete)
   float* wr;   // write buffer
-  double r;    // shift: V = W + r
 };
 
 __device__ __forceinline__ double cost_of(const KParams& p, int64_t row) {
   return p.ceff ? p.ceff[row] : (double)p.c32[row];
 }
 
-// New value of state s from the FP64 bracket minimum q with action a.
+// New value of state s from the FP64 bracket minimum q with action a.  The
+// solvers iterate W = V - R for an FP64 anchor R (see Driver::recentre);
+// the error against V_ref is taken on W + R.
 __device__ __forceinline__ void commit_sweep(const KParams& p, const Ctx& c, int32_t s, double q,
-                                             int a, Local& L) {
-  const float old = c.rd[s];
+                                             int a, float old, Local& L) {
   const float w = (float)q;
   c.wr[s] = w;
   if (p.argmin_out) p.argmin_out[s] = a;
   L.dv = fmax(L.dv, fabs((double)w - (double)old));
-  if (p.vref) L.err = fmax(L.err, fabs(((double)w + c.r) - p.vref[s]));
+  if (p.vref) L.err = fmax(L.err, fabs(((double)w + (p.shift ? p.shift[s] : 0.0)) - p.vref[s]));
   L.wmax = fmax(L.wmax, (double)w);
   L.wmin = fmin(L.wmin, (double)w);
 }
 
 // Policy improvement of state s (Algorithm 1): V is not written.
-__device__ __forceinline__ void commit_improve(const KParams& p, const Ctx& c, int32_t s, double q,
-                                               int a, bool count, Local& L) {
+__device__ __forceinline__ void commit_improve(const KParams& p, int32_t s, double q, int a,
+                                               float old, bool count, Local& L) {
   if (count && p.policy[s] != a) L.changes += 1;
   p.policy[s] = a;
-  L.resid = fmax(L.resid, fabs(q - (double)c.rd[s]));
+  L.resid = fmax(L.resid, fabs(q - (double)old));
 }
 
 enum Mode : int { kModeMin = 0, kModePolicy = 1, kModeImprove = 2, kModeImproveCount = 3 };
@@ -214,6 +220,25 @@ __device__ __forceinline__ void block_sum(float (&acc)[R], float* out) {
   if (threadIdx.x < R) {
     float s = 0.f;
     for (int i = 0; i < nw; ++i) s += red[i][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// out[r] (LDS) = block-wide FP64 sum of acc[r], r < R.
+template <int R>
+__device__ __forceinline__ void block_sum_d(double (&acc)[R], double* out) {
+  __shared__ double red_d[16][16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double v = wave_sum_d(acc[r]);
+    if (lane == 0) red_d[w][r] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < R) {
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += red_d[i][threadIdx.x];
     out[threadIdx.x] = s;
   }
   __syncthreads();
@@ -334,28 +359,43 @@ struct DenseEngine {
           if (av == 0x7fffffff) av = 0;
         }
         if (threadIdx.x == 0) {
+          const float old = c.rd[s];
           if (improve)
-            commit_improve(p, c, s, qv, av, mode == kModeImproveCount, L);
+            commit_improve(p, s, qv, av, old, mode == kModeImproveCount, L);
           else
-            commit_sweep(p, c, s, qv, av, L);
+            commit_sweep(p, c, s, qv, av, old, L);
         }
       }
       __syncthreads();
     }
   }
 
-  // rho(s,a) = sum_s' P(s,a,s') in FP64, one wavefront per row.
-  __device__ __forceinline__ static void row_sums(const KParams& p) {
-    const int64_t rows = p.n * p.m;
-    const int lane = threadIdx.x & 63;
-    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t r = gw; r < rows; r += nw) {
-      const float* row = p.P + (size_t)r * (size_t)p.n;
-      double s = 0.0;
-      for (int64_t j = lane; j < p.n; j += kWave) s += (double)__builtin_nontemporal_load(row + j);
-      s = wave_sum_d(s);
-      if (lane == 0) p.rho[r] = s;
+  // c'(s,a) = c(s,a) - R(s) + gamma * (P R)(s,a) in FP64, a workgroup per state.
+  __device__ __forceinline__ static void shift_costs(const KParams& p) {
+    __shared__ double s_sumd[16];
+    const int m = p.m;
+    const uint32_t n = (uint32_t)p.n;
+    for (int64_t s = blockIdx.x; s < p.n; s += gridDim.x) {
+      const double rs = p.shift[s];
+      for (int a0 = 0; a0 < m; a0 += R) {
+        const int nrows = min(R, m - a0);
+        const float* rows = p.P + ((size_t)s * m + a0) * (size_t)n;
+        double acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0.0;
+        for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
+          const double rj = p.shift[j];
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if (r < nrows)
+              acc[r] = fma((double)__builtin_nontemporal_load(rows + (size_t)r * n + j), rj, acc[r]);
+        }
+        block_sum_d<R>(acc, s_sumd);
+        if (threadIdx.x < nrows) {
+          const int64_t row = (int64_t)s * m + a0 + threadIdx.x;
+          p.ceff[row] = (double)p.c32[row] - rs + p.gamma * s_sumd[threadIdx.x];
+        }
+      }
     }
   }
 };
@@ -374,6 +414,11 @@ struct EllEngine {
     return lpr;
   }
 
+  // One wavefront iteration serves UNR states (min modes) or UNR lane
+  // groups of states (policy mode).  The states of the next iteration are
+  // fetched one iteration ahead, and the costs and old values are loaded
+  // together with the columns and weights, so an iteration waits for two
+  // round trips (the row stream, then the V gathers).
   __device__ __forceinline__ static void batch(const KParams& p, const int32_t* ord, int64_t bk,
                                                const Ctx& c, int mode, Local& L) {
     const int m = p.m, k = p.ell_k;
@@ -383,19 +428,29 @@ struct EllEngine {
     const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
     const bool improve = mode >= kModeImprove;
-    if (mode == kModePolicy) {
-      const int64_t per_unit = (int64_t)rpp * UNR;
-      const int64_t units = (bk + per_unit - 1) / per_unit;
-      for (int64_t u = gw; u < units; u += nw) {
-        int32_t s[UNR];
+    const bool pol = mode == kModePolicy;
+    // positions of a unit: min modes UNR states, policy mode UNR groups of rpp
+    const int64_t per_unit = pol ? (int64_t)rpp * UNR : (int64_t)UNR;
+    const int64_t units = (bk + per_unit - 1) / per_unit;
+    auto state_at = [&](int64_t u, int x) -> int32_t {
+      const int64_t pos = pol ? u * per_unit + (int64_t)x * rpp + g : u * per_unit + x;
+      return (u < units && pos < bk) ? (ord ? ord[pos] : (int32_t)pos) : -1;
+    };
+    int32_t s_next[UNR];
+#pragma unroll
+    for (int x = 0; x < UNR; ++x) s_next[x] = state_at(gw, x);
+    for (int64_t u = gw; u < units; u += nw) {
+      int32_t s[UNR];
+#pragma unroll
+      for (int x = 0; x < UNR; ++x) s[x] = s_next[x];
+      float old[UNR];
+#pragma unroll
+      for (int x = 0; x < UNR; ++x) old[x] = s[x] >= 0 ? c.rd[s[x]] : 0.f;
+      if (pol) {
         int a[UNR];
         i4 cc[UNR];
         f4 vv[UNR];
-#pragma unroll
-        for (int x = 0; x < UNR; ++x) {
-          const int64_t pos = u * per_unit + (int64_t)x * rpp + g;
-          s[x] = pos < bk ? (ord ? ord[pos] : (int32_t)pos) : -1;
-        }
+        double cost[UNR];
 #pragma unroll
         for (int x = 0; x < UNR; ++x) {
           a[x] = s[x] >= 0 ? p.policy[s[x]] : 0;
@@ -403,15 +458,16 @@ struct EllEngine {
             raise_abort(p.ctl, kDevBadPolicy);
             a[x] = 0;
           }
-          if (s[x] >= 0 && lane_has_data) {
-            const size_t e = ((size_t)s[x] * m + a[x]) * (size_t)k + (size_t)l * 4;
-            cc[x] = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e));
-            vv[x] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e));
-          } else {
-            cc[x] = i4{0, 0, 0, 0};
-            vv[x] = f4{0.f, 0.f, 0.f, 0.f};
-          }
+          const bool ok = s[x] >= 0 && lane_has_data;
+          const size_t e = ((size_t)(ok ? s[x] : 0) * m + a[x]) * (size_t)k + (size_t)l * 4;
+          cc[x] = ok ? __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e))
+                     : i4{0, 0, 0, 0};
+          vv[x] = ok ? __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e))
+                     : f4{0.f, 0.f, 0.f, 0.f};
+          cost[x] = s[x] >= 0 ? cost_of(p, (int64_t)s[x] * m + a[x]) : 0.0;
         }
+#pragma unroll
+        for (int x = 0; x < UNR; ++x) s_next[x] = state_at(u + nw, x);
 #pragma unroll
         for (int x = 0; x < UNR; ++x) {
           float part = vv[x].x * c.rd[cc[x].x];
@@ -419,41 +475,39 @@ struct EllEngine {
           part = fmaf(vv[x].z, c.rd[cc[x].z], part);
           part = fmaf(vv[x].w, c.rd[cc[x].w], part);
           for (int off = lpr >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
-          if (l == 0 && s[x] >= 0) {
-            const double q = cost_of(p, (int64_t)s[x] * m + a[x]) + p.gamma * (double)part;
-            commit_sweep(p, c, s[x], q, a[x], L);
-          }
+          if (l == 0 && s[x] >= 0)
+            commit_sweep(p, c, s[x], cost[x] + p.gamma * (double)part, a[x], old[x], L);
         }
+        continue;
       }
-      return;
-    }
-    const int64_t units = (bk + UNR - 1) / UNR;
-    for (int64_t u = gw; u < units; u += nw) {
-      int32_t s[UNR];
       double qb[UNR];
       int ab[UNR];
 #pragma unroll
       for (int x = 0; x < UNR; ++x) {
-        const int64_t pos = u * UNR + x;
-        s[x] = pos < bk ? (ord ? ord[pos] : (int32_t)pos) : -1;
         qb[x] = INFINITY;
         ab[x] = 0x7fffffff;
       }
+      bool prefetched = false;
       for (int a0 = 0; a0 < m; a0 += rpp) {
         const int a = a0 + g;
         const bool row_ok = a < m && lane_has_data;
         i4 cc[UNR];
         f4 vv[UNR];
+        double cost[UNR];
 #pragma unroll
         for (int x = 0; x < UNR; ++x) {
-          if (row_ok && s[x] >= 0) {
-            const size_t e = ((size_t)s[x] * m + a) * (size_t)k + (size_t)l * 4;
-            cc[x] = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e));
-            vv[x] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e));
-          } else {
-            cc[x] = i4{0, 0, 0, 0};
-            vv[x] = f4{0.f, 0.f, 0.f, 0.f};
-          }
+          const bool ok = row_ok && s[x] >= 0;
+          const size_t e = ((size_t)(ok ? s[x] : 0) * m + a) * (size_t)k + (size_t)l * 4;
+          cc[x] = ok ? __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e))
+                     : i4{0, 0, 0, 0};
+          vv[x] = ok ? __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e))
+                     : f4{0.f, 0.f, 0.f, 0.f};
+          cost[x] = (a < m && s[x] >= 0) ? cost_of(p, (int64_t)s[x] * m + a) : INFINITY;
+        }
+        if (!prefetched) {
+#pragma unroll
+          for (int x = 0; x < UNR; ++x) s_next[x] = state_at(u + nw, x);
+          prefetched = true;
         }
 #pragma unroll
         for (int x = 0; x < UNR; ++x) {
@@ -465,7 +519,7 @@ struct EllEngine {
           double q = INFINITY;
           int aq = 0x7fffffff;
           if (a < m && s[x] >= 0) {
-            q = cost_of(p, (int64_t)s[x] * m + a) + p.gamma * (double)part;
+            q = cost[x] + p.gamma * (double)part;
             aq = a;
           }
           wave_argmin(q, aq, lpr);
@@ -481,23 +535,40 @@ struct EllEngine {
           if (s[x] < 0) continue;
           const int av = ab[x] == 0x7fffffff ? 0 : ab[x];
           if (improve)
-            commit_improve(p, c, s[x], qb[x], av, mode == kModeImproveCount, L);
+            commit_improve(p, s[x], qb[x], av, old[x], mode == kModeImproveCount, L);
           else
-            commit_sweep(p, c, s[x], qb[x], av, L);
+            commit_sweep(p, c, s[x], qb[x], av, old[x], L);
         }
       }
     }
   }
 
-  // rho = row sums in FP64, one thread per row.
-  __device__ __forceinline__ static void row_sums(const KParams& p) {
-    const int64_t rows = p.n * p.m;
-    const int k = p.ell_k;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows;
-         r += (int64_t)gridDim.x * blockDim.x) {
-      double s = 0.0;
-      for (int e = 0; e < k; ++e) s += (double)p.val[(size_t)r * k + e];
-      p.rho[r] = s;
+  // c'(s,a) = c(s,a) - R(s) + gamma * (P R)(s,a) in FP64, a wavefront per state.
+  __device__ __forceinline__ static void shift_costs(const KParams& p) {
+    const int m = p.m, k = p.ell_k;
+    const int lpr = lanes_per_row(k), rpp = kWave / lpr;
+    const int lane = threadIdx.x & 63, g = lane / lpr, l = lane % lpr;
+    const bool lane_has_data = l * 4 < k;
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t s = gw; s < p.n; s += nw) {
+      const double rs = p.shift[s];
+      for (int a0 = 0; a0 < m; a0 += rpp) {
+        const int a = a0 + g;
+        double part = 0.0;
+        if (a < m && lane_has_data) {
+          const size_t e = ((size_t)s * m + a) * (size_t)k + (size_t)l * 4;
+          const i4 cc = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e));
+          const f4 vv = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e));
+          part = (double)vv.x * p.shift[cc.x] + (double)vv.y * p.shift[cc.y] +
+                 (double)vv.z * p.shift[cc.z] + (double)vv.w * p.shift[cc.w];
+        }
+        for (int off = lpr >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
+        if (l == 0 && a < m) {
+          const int64_t row = s * m + a;
+          p.ceff[row] = (double)p.c32[row] - rs + p.gamma * part;
+        }
+      }
     }
   }
 };
@@ -537,21 +608,30 @@ struct CsrEngine {
       }
       if (ab == 0x7fffffff) ab = a_lo;
       if (lane == 0) {
+        const float old = c.rd[s];
         if (improve)
-          commit_improve(p, c, s, qb, ab, mode == kModeImproveCount, L);
+          commit_improve(p, s, qb, ab, old, mode == kModeImproveCount, L);
         else
-          commit_sweep(p, c, s, qb, ab, L);
+          commit_sweep(p, c, s, qb, ab, old, L);
       }
     }
   }
 
-  __device__ __forceinline__ static void row_sums(const KParams& p) {
-    const int64_t rows = p.n * p.m;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows;
-         r += (int64_t)gridDim.x * blockDim.x) {
-      double s = 0.0;
-      for (int64_t e = p.row_ptr[r]; e < p.row_ptr[r + 1]; ++e) s += (double)p.val[e];
-      p.rho[r] = s;
+  // c'(s,a) = c(s,a) - R(s) + gamma * (P R)(s,a) in FP64, a wavefront per state.
+  __device__ __forceinline__ static void shift_costs(const KParams& p) {
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t s = gw; s < p.n; s += nw) {
+      const double rs = p.shift[s];
+      for (int a = 0; a < p.m; ++a) {
+        const int64_t row = s * p.m + a;
+        double part = 0.0;
+        for (int64_t e = p.row_ptr[row] + lane; e < p.row_ptr[row + 1]; e += kWave)
+          part = fma((double)p.val[e], p.shift[p.col[e]], part);
+        part = wave_sum_d(part);
+        if (lane == 0) p.ceff[row] = (double)p.c32[row] - rs + p.gamma * part;
+      }
     }
   }
 };
@@ -567,7 +647,6 @@ struct Driver {
   int64_t phase;          // batches processed (parity selects the read buffer)
   const int32_t* prev_order;
   int64_t prev_count;     // states of the previous batch still to copy forward
-  double r;               // V = W + r
   unsigned epoch;         // sweeps + improvement passes, selects accumulator slot
   int64_t gtid, gthreads;
 
@@ -582,30 +661,42 @@ struct Driver {
     phase = 0;
     prev_order = nullptr;
     prev_count = 0;
-    r = 0.0;
     epoch = 0;
     gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     gthreads = (int64_t)gridDim.x * blockDim.x;
   }
 
+  // Stamp of sweep t in first_mark (never 0, the cleared value).
+  __device__ __forceinline__ static uint32_t stamp(uint64_t t) {
+    const uint32_t v = (uint32_t)(t + 1);
+    return v ? v : 1u;
+  }
+
   // order[t % 3][pos] for pos in [begin, begin + count): sigma_t or perm.
+  // The states of a sweep's first batch (begin == 0) are stamped.
   __device__ __forceinline__ void fill_order(uint64_t t, int64_t begin, int64_t count) {
     int32_t* dst = p.order + (size_t)(t % 3) * (size_t)p.n;
+    const bool first = begin == 0;
+    const uint32_t st = stamp(t);
+    uint32_t* mark = p.first_mark + (size_t)(t & 1) * (size_t)p.n;
     if (p.perm) {
       for (int64_t i = gtid; i < count; i += gthreads) {
-        const int32_t v = p.perm[begin + i];
+        int32_t v = p.perm[begin + i];
         if (v < 0 || (int64_t)v >= p.n) {
           raise_abort(p.ctl, kDevBadPerm);
-          dst[begin + i] = 0;
-        } else {
-          dst[begin + i] = v;
+          v = 0;
         }
+        dst[begin + i] = v;
+        if (first) mark[v] = st;
       }
       return;
     }
     const OrderKey key = make_order_key(p.n, p.seed, t);
-    for (int64_t i = gtid; i < count; i += gthreads)
-      dst[begin + i] = (int32_t)sweep_order_at((uint32_t)(begin + i), key);
+    for (int64_t i = gtid; i < count; i += gthreads) {
+      const int32_t v = (int32_t)sweep_order_at((uint32_t)(begin + i), key);
+      dst[begin + i] = v;
+      if (first) mark[v] = st;
+    }
   }
 
   // buffer holding V before the current batch (complete) / the other one
@@ -621,10 +712,14 @@ struct Driver {
     const int32_t* ord = p.order + (size_t)(t % 3) * (size_t)n;
     for (int64_t k = 0; k < nb; ++k) {
       const int64_t kb = k * b, bk = min(b, n - kb);
-      Ctx c{rd_buf(), wr_buf(), r};
+      Ctx c{rd_buf(), wr_buf()};
+      // copy the previous batch forward, except states this batch rewrites
+      // (only possible for the first batch, whose states are stamped)
+      const uint32_t st = stamp(t);
+      const uint32_t* mark = p.first_mark + (size_t)(t & 1) * (size_t)n;
       for (int64_t i = gtid; i < prev_count; i += gthreads) {
         const int32_t s = prev_order[i];
-        c.wr[s] = c.rd[s];
+        if (k != 0 || mark[s] != st) c.wr[s] = c.rd[s];
       }
       if (k + 1 < nb)
         fill_order(t, kb + b, min(b, n - kb - b));
@@ -644,7 +739,7 @@ struct Driver {
   template <class Eng>
   __device__ __forceinline__ bool improve(bool count) {
     if (blockIdx.x == 0 && threadIdx.x == 0) reset_slot(p.ctl, (int)((epoch + 1) % 3));
-    Ctx c{rd_buf(), wr_buf(), r};
+    Ctx c{rd_buf(), wr_buf()};
     Eng::batch(p, nullptr, p.n, c, count ? kModeImproveCount : kModeImprove, L);
     flush_local(L, p.ctl, slot());
     if (!grid_sync(g)) return false;
@@ -652,36 +747,57 @@ struct Driver {
     return true;
   }
 
-  // Shift both buffers by the midpoint of the last sweep's values and
-  // rebuild the shifted costs (re-centring; exact in real arithmetic).
-  __device__ __forceinline__ bool recentre(int last_slot, long long& count) {
-    const double wmax = okey_value(atomic_load_agent(&p.ctl->acc[last_slot][kAccWmax]));
-    const double wmin = okey_value(atomic_load_agent(&p.ctl->acc[last_slot][kAccWmin]));
-    const double delta = 0.5 * (wmax + wmin);
-    if (!isfinite(delta) || delta == 0.0) return true;
-    r += delta;
+  // Re-centring (exact in real arithmetic): fold the iterate into the FP64
+  // anchor, R <- R + W, set W = 0 in both buffers, and rebuild the shifted
+  // costs c'(s,a) = c(s,a) - R(s) + gamma (P R)(s,a).  Every value a state
+  // reads is V(j) = W(j) + R(j), old or new alike, so the sweep on W with c'
+  // is the sweep on V minus R for any order and batch size.  Afterwards W
+  // carries only the change since the fold, so FP32 resolves it relative to
+  // the remaining error rather than to |V|.
+  template <class Eng>
+  __device__ __forceinline__ bool recentre(long long& count) {
+    const float* cur = rd_buf();
     for (int64_t s = gtid; s < p.n; s += gthreads) {
-      buf0[s] = (float)((double)buf0[s] - delta);
-      buf1[s] = (float)((double)buf1[s] - delta);
+      p.shift[s] += (double)cur[s];
+      buf0[s] = 0.f;
+      buf1[s] = 0.f;
     }
-    const int64_t rows = p.n * p.m;
-    for (int64_t i = gtid; i < rows; i += gthreads)
-      p.ceff[i] = (double)p.c32[i] - r + p.gamma * r * p.rho[i];
+    if (!grid_sync(g)) return false;
+    Eng::shift_costs(p);
     ++count;
     return grid_sync(g);
   }
 
-  // Final V into the caller's buffer (V = W + r) and the statistics.
+  // True when FP32 resolution of W is about to limit the iteration: the
+  // last sweep changed W by less than 2^-14 of its magnitude.
+  __device__ __forceinline__ bool want_recentre(int slot_, double last_dv, long long since) const {
+    if (p.recentre_every <= 0 || since < p.recentre_every) return false;
+    const double wmax = okey_value(atomic_load_agent(&p.ctl->acc[slot_][kAccWmax]));
+    const double wmin = okey_value(atomic_load_agent(&p.ctl->acc[slot_][kAccWmin]));
+    const double wabs = fmax(fabs(wmax), fabs(wmin));
+    if (!isfinite(wabs) || wabs <= 0.0) return false;
+    return p.recentre_force || wabs > 16384.0 * last_dv;
+  }
+
+  // Final V into the caller's buffer (V = W + R) and the statistics.
   __device__ __forceinline__ void finish(long long sweeps, long long outer, long long changes_last,
-                         long long recentrings, double last_dv, double last_err, int converged) {
-    float* cur = rd_buf();
-    if (r != 0.0) {
-      for (int64_t s = gtid; s < p.n; s += gthreads) p.vbuf0[s] = (float)((double)cur[s] + r);
-    } else if (cur != p.vbuf0) {
-      for (int64_t i = gtid; i < prev_count; i += gthreads) {
-        const int32_t s = prev_order[i];
-        p.vbuf0[s] = cur[s];
+                                         long long recentrings, double last_dv, double last_err,
+                                         int converged) {
+    const float* cur = rd_buf();
+    if (p.shift) {
+      for (int64_t s = gtid; s < p.n; s += gthreads) {
+        const double v = (double)cur[s] + p.shift[s];
+        p.vbuf0[s] = (float)v;
+        if (p.v64_out) p.v64_out[s] = v;
       }
+    } else {
+      if (cur != p.vbuf0)
+        for (int64_t i = gtid; i < prev_count; i += gthreads) {
+          const int32_t s = prev_order[i];
+          p.vbuf0[s] = cur[s];
+        }
+      if (p.v64_out)
+        for (int64_t s = gtid; s < p.n; s += gthreads) p.v64_out[s] = (double)cur[s];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       Control* ctl = p.ctl;
@@ -691,7 +807,6 @@ struct Driver {
       ctl->recentrings = recentrings;
       ctl->final_dv_inf = last_dv;
       ctl->final_err_ref = last_err;
-      ctl->shift = r;
       ctl->converged = converged;
       ctl->dv_last = (float)last_dv;
     }
@@ -706,9 +821,10 @@ __global__ void __launch_bounds__(1024) solve_kernel(KParams p) {
   // prologue: second buffer, row sums and shifted costs, first order
   for (int64_t s = d.gtid; s < n; s += d.gthreads) p.vbuf1[s] = p.vbuf0[s];
   if (TASK != kTaskSweep && p.recentre_every > 0) {
-    Eng::row_sums(p);
+    for (int64_t s = d.gtid; s < n; s += d.gthreads) p.shift[s] = 0.0;
     for (int64_t i = d.gtid; i < n * p.m; i += d.gthreads) p.ceff[i] = (double)p.c32[i];
   }
+  long long since_recentre = 0;
   d.fill_order(t, 0, min(p.b, n));
   if (blockIdx.x == 0 && threadIdx.x == 0) reset_slot(p.ctl, 0);
   if (!grid_sync(d.g)) return;
@@ -739,8 +855,10 @@ __global__ void __launch_bounds__(1024) solve_kernel(KParams p) {
         break;
       }
       if (sweeps >= p.max_sweeps) break;
-      if (p.recentre_every > 0 && sweeps % p.recentre_every == 0)
-        if (!d.recentre(sl, recentrings)) return;
+      if (d.want_recentre(sl, last_dv, ++since_recentre)) {
+        if (!d.template recentre<Eng>(recentrings)) return;
+        since_recentre = 0;
+      }
     }
     if (p.want_policy_out)
       if (!d.template improve<Eng>(false)) return;
@@ -762,8 +880,10 @@ __global__ void __launch_bounds__(1024) solve_kernel(KParams p) {
             break;
           }
         }
-        if (p.recentre_every > 0 && sweeps % p.recentre_every == 0)
-          if (!d.recentre(sl, recentrings)) return;
+        if (d.want_recentre(sl, slot_double(p.ctl, sl, kAccDv), ++since_recentre)) {
+          if (!d.template recentre<Eng>(recentrings)) return;
+          since_recentre = 0;
+        }
       }
       if (done) break;
       if (!d.template improve<Eng>(true)) return;
@@ -913,7 +1033,7 @@ static SolveFn pick(const KParams& p, int units_per_wave_hint) {
     return solve_fn<DenseEngine<1, 1>>(p.task);
   }
   if (p.storage == kEll) {
-    if (units_per_wave_hint >= 4) return solve_fn<EllEngine<4>>(p.task);
+    // two states per wavefront iteration keep the pipelined loop within 128 VGPRs
     if (units_per_wave_hint >= 2) return solve_fn<EllEngine<2>>(p.task);
     return solve_fn<EllEngine<1>>(p.task);
   }

@@ -107,9 +107,10 @@ LaunchShape shape_of(const mbdp_mdp* h) {
   return s;
 }
 
+// Minimum sweeps between re-centrings (0: no FP64 anchor).
 int recentre_interval(const mbdp_mdp* h) {
   if (h->tuning.recentre_every < 0) return 0;
-  return h->tuning.recentre_every > 0 ? h->tuning.recentre_every : 32;
+  return h->tuning.recentre_every > 0 ? h->tuning.recentre_every : 8;
 }
 
 KParams base_params(const mbdp_mdp* h, void* ws, float* V, int64_t b) {
@@ -131,6 +132,7 @@ KParams base_params(const mbdp_mdp* h, void* ws, float* V, int64_t b) {
   p.b = b;
   p.ctl = reinterpret_cast<Control*>(base + w.ctl);
   p.order = reinterpret_cast<int32_t*>(base + w.order);
+  p.first_mark = reinterpret_cast<uint32_t*>(base + w.first_mark);
   p.partial = reinterpret_cast<float*>(base + w.partial);
   p.unit_count = reinterpret_cast<unsigned int*>(base + w.unit_count);
   p.timeout_ticks = (unsigned long long)(kBarrierTimeoutSeconds * 1000.0 * (double)h->wall_khz);
@@ -175,7 +177,6 @@ void fill_stats(const Control& c, bool with_ref, mbdp_stats* st) {
   st->recentrings = c.recentrings;
   st->final_dv_inf = c.final_dv_inf;
   st->final_err_ref = with_ref ? c.final_err_ref : NAN;
-  st->shift = c.shift;
   st->converged = c.converged;
   st->reserved = 0;
 }
@@ -384,10 +385,10 @@ mbdp_status mbdp_sync_status(void* workspace, size_t ws_bytes, hipStream_t strea
   return finish(workspace, stream, &c);
 }
 
-mbdp_status vi_solve(mbdp_mdp_t h, float* V, int32_t* policy_out, int64_t b, uint64_t seed,
-                     uint64_t first_sweep, double tol_dv, double eps, const double* V_ref,
-                     int64_t max_sweeps, void* workspace, size_t ws_bytes, hipStream_t stream,
-                     mbdp_stats* stats) {
+mbdp_status vi_solve(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy_out, int64_t b,
+                     uint64_t seed, uint64_t first_sweep, double tol_dv, double eps,
+                     const double* V_ref, int64_t max_sweeps, void* workspace, size_t ws_bytes,
+                     hipStream_t stream, mbdp_stats* stats) {
   if (!h) return fail(MBDP_ERR_INVALID_ARG, "handle is NULL");
   if (!V) return fail(MBDP_ERR_INVALID_ARG, "V is NULL");
   if (b < 1 || b > h->n)
@@ -401,6 +402,7 @@ mbdp_status vi_solve(mbdp_mdp_t h, float* V, int32_t* policy_out, int64_t b, uin
   const WsLayout w = layout(h);
   KParams p = base_params(h, workspace, V, b);
   p.task = kTaskVI;
+  p.v64_out = V64_out;
   p.policy = policy_out;
   p.want_policy_out = policy_out != nullptr;
   p.seed = seed;
@@ -410,9 +412,10 @@ mbdp_status vi_solve(mbdp_mdp_t h, float* V, int32_t* policy_out, int64_t b, uin
   p.vref = V_ref;
   p.max_sweeps = max_sweeps;
   p.recentre_every = recentre_interval(h);
+  p.recentre_force = h->tuning.recentre_force != 0;
   if (p.recentre_every > 0) {
     p.ceff = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.ceff);
-    p.rho = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.rho);
+    p.shift = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.shift);
   }
   st = launch(h, p, workspace, stream);
   if (st != MBDP_OK) return st;
@@ -426,10 +429,11 @@ mbdp_status vi_solve(mbdp_mdp_t h, float* V, int32_t* policy_out, int64_t b, uin
   return MBDP_OK;
 }
 
-mbdp_status mpi_solve(mbdp_mdp_t h, float* V, int32_t* policy, int32_t policy_is_init, int32_t K,
-                      int64_t b, uint64_t seed, uint64_t first_sweep, double tol_dv, double eps,
-                      const double* V_ref, int64_t max_outer, void* workspace, size_t ws_bytes,
-                      hipStream_t stream, mbdp_stats* stats) {
+mbdp_status mpi_solve(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy,
+                      int32_t policy_is_init, int32_t K, int64_t b, uint64_t seed,
+                      uint64_t first_sweep, double tol_dv, double eps, const double* V_ref,
+                      int64_t max_outer, void* workspace, size_t ws_bytes, hipStream_t stream,
+                      mbdp_stats* stats) {
   if (!h) return fail(MBDP_ERR_INVALID_ARG, "handle is NULL");
   if (!V || !policy) return fail(MBDP_ERR_INVALID_ARG, "V or policy is NULL");
   if (K < 1) return fail(MBDP_ERR_INVALID_ARG, "K = %d < 1", K);
@@ -444,6 +448,7 @@ mbdp_status mpi_solve(mbdp_mdp_t h, float* V, int32_t* policy, int32_t policy_is
   const WsLayout w = layout(h);
   KParams p = base_params(h, workspace, V, b);
   p.task = kTaskMPI;
+  p.v64_out = V64_out;
   p.policy = policy;
   p.policy_is_init = policy_is_init != 0;
   p.K = K;
@@ -454,9 +459,10 @@ mbdp_status mpi_solve(mbdp_mdp_t h, float* V, int32_t* policy, int32_t policy_is
   p.vref = V_ref;
   p.max_outer = max_outer;
   p.recentre_every = recentre_interval(h);
+  p.recentre_force = h->tuning.recentre_force != 0;
   if (p.recentre_every > 0) {
     p.ceff = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.ceff);
-    p.rho = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.rho);
+    p.shift = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.shift);
   }
   st = launch(h, p, workspace, stream);
   if (st != MBDP_OK) return st;

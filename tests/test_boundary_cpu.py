@@ -100,10 +100,10 @@ def test_calls_on_a_null_handle(lib):
     assert lib.mdp_validate(NULL, 1e-6, DUMMY, 1 << 20, NULL, None) == binding.MBDP_ERR_INVALID_ARG
     assert lib.mb_sweep(NULL, DUMMY, NULL, 1, 0, 0, NULL, NULL, NULL, DUMMY, 1 << 20, NULL) == \
         binding.MBDP_ERR_INVALID_ARG
-    assert lib.vi_solve(NULL, DUMMY, NULL, 1, 0, 0, 1e-8, 0.0, NULL, 10, DUMMY, 1 << 20, NULL,
-                        ctypes.byref(st)) == binding.MBDP_ERR_INVALID_ARG
-    assert lib.mpi_solve(NULL, DUMMY, DUMMY, 1, 5, 1, 0, 0, 1e-8, 0.0, NULL, 10, DUMMY, 1 << 20,
-                         NULL, ctypes.byref(st)) == binding.MBDP_ERR_INVALID_ARG
+    assert lib.vi_solve(NULL, DUMMY, NULL, NULL, 1, 0, 0, 1e-8, 0.0, NULL, 10, DUMMY, 1 << 20,
+                        NULL, ctypes.byref(st)) == binding.MBDP_ERR_INVALID_ARG
+    assert lib.mpi_solve(NULL, DUMMY, NULL, DUMMY, 1, 5, 1, 0, 0, 1e-8, 0.0, NULL, 10, DUMMY,
+                         1 << 20, NULL, ctypes.byref(st)) == binding.MBDP_ERR_INVALID_ARG
     assert lib.mbdp_sync_status(NULL, 0, NULL) == binding.MBDP_ERR_WORKSPACE
 
 

@@ -62,10 +62,12 @@ def test_dense_8192x16_vi_reaches_eps(c2, b):
     wl, h, mdp, Vstar = c2
     ws = mb.workspace(h, b)
     V = torch.zeros(wl["n"], dtype=torch.float32, device=dev())
+    V64 = torch.zeros(wl["n"], dtype=torch.float64, device=dev())
     st = mb.vi_solve(h, V, b, wl["perm_seed"], ws, tol_dv=-1.0, eps=1e-6, V_ref=up(Vstar),
-                     max_sweeps=5000)
+                     max_sweeps=5000, V64_out=V64)
     say("VI b=%d: %s" % (b, st))
     assert st["converged"]
+    assert np.max(np.abs(V64.cpu().numpy() - Vstar)) <= 1e-6
     assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= out_tol(1e-6, Vstar)
 
 
@@ -113,22 +115,26 @@ def test_sparse_1M_policy_sweep(c3):
     run_sweep(h, mdp, V0, 65536, wl["perm_seed"], 1, policy=inputs.policy(wl["n"], wl["m"], 23))
 
 
-def test_sparse_1M_vi_limit_is_a_fixed_point(c3):
-    """Run MB-VI until the FP32 iterate stops moving; its oracle Bellman
-    residual max|TV - V| must be at the level of FP32 rounding of V, which
-    bounds max|V - J*| by residual / (1 - gamma) (contraction, Sec. III-B)."""
+def test_sparse_1M_vi_certified_eps(c3):
+    """MB-VI at b = 65536 until max|dV| <= 1e-11, then the oracle's Bellman
+    residual of the FP64 iterate certifies the accuracy at full size:
+    max|V - J*| <= max|TV - V| / (1 - gamma) (contraction, Sec. III-B)."""
     wl, h, mdp = c3
+    n = wl["n"]
     ws = mb.workspace(h, 65536)
-    V = torch.zeros(wl["n"], dtype=torch.float32, device=dev())
+    V = torch.zeros(n, dtype=torch.float32, device=dev())
+    V64 = torch.zeros(n, dtype=torch.float64, device=dev())
     t0 = time.time()
-    st = mb.vi_solve(h, V, 65536, wl["perm_seed"], ws, tol_dv=0.0, max_sweeps=6000)
-    say("VI to FP32 fixed point: %s in %.1f s" % (st, time.time() - t0))
-    Vg = V.cpu().numpy().astype(np.float64)
+    st = mb.vi_solve(h, V, 65536, wl["perm_seed"], ws, tol_dv=1e-11, max_sweeps=20000,
+                     V64_out=V64)
+    say("VI to max|dV| <= 1e-11: %s in %.1f s" % (st, time.time() - t0))
+    assert st["converged"]
+    Vg = V64.cpu().numpy()
     TV, _ = oracle.greedy(mdp, Vg)
     resid = float(np.max(np.abs(TV - Vg)))
-    ulp = float(np.spacing(np.float32(np.max(np.abs(Vg)))))
-    say("oracle residual %.3g (ulp(V) = %.3g)" % (resid, ulp))
-    assert resid <= 2 * ulp
+    bound = resid / (1.0 - wl["gamma"])
+    say("oracle residual %.3g -> certified max|V - J*| <= %.3g" % (resid, bound))
+    assert bound <= 1e-6
 
 
 def test_sparse_50k_reaches_eps():
@@ -142,10 +148,12 @@ def test_sparse_50k_reaches_eps():
     for b in (4096, n):
         ws = mb.workspace(h, b)
         V = torch.zeros(n, dtype=torch.float32, device=dev())
+        V64 = torch.zeros(n, dtype=torch.float64, device=dev())
         st = mb.vi_solve(h, V, b, 103, ws, tol_dv=-1.0, eps=1e-6, V_ref=up(Vstar),
-                         max_sweeps=20000)
+                         max_sweeps=20000, V64_out=V64)
         say("VI b=%d: %s" % (b, st))
         assert st["converged"]
+        assert np.max(np.abs(V64.cpu().numpy() - Vstar)) <= 1e-6
         assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= out_tol(1e-6, Vstar)
 
 

@@ -61,11 +61,114 @@ def test_vi_first_crossing_matches_oracle(c1, b):
     h, mdp, Vstar = c1
     ws = mb.workspace(h, b)
     V = zeros(64)
-    st = mb.vi_solve(h, V, b, 101, ws, tol_dv=-1.0, eps=1e-6, V_ref=up(Vstar), max_sweeps=5000)
+    V64 = zeros(64, torch.float64)
+    st = mb.vi_solve(h, V, b, 101, ws, tol_dv=-1.0, eps=1e-6, V_ref=up(Vstar), max_sweeps=5000,
+                     V64_out=V64)
     _, _, ost = oracle.value_iteration(mdp, b, 101, tol_dv=-1, V_ref=Vstar, eps=1e-6)
     assert st["converged"] and st["final_err_ref"] <= 1e-6
+    assert np.max(np.abs(V64.cpu().numpy() - Vstar)) <= 1e-6
     assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= out_tol(1e-6, Vstar)
     assert abs(st["sweeps"] - ost.sweeps) <= 2, (st["sweeps"], ost.sweeps)
+
+
+@pytest.mark.parametrize("b", [1, 16, 64])
+def test_vi_tight_tolerance_beyond_fp32(c1, b):
+    """With the FP64 anchor the iterate keeps converging far below FP32
+    resolution of V: max|dV| <= 1e-12 certifies max|V - J*| <= 9e-12."""
+    h, mdp, Vstar = c1
+    ws = mb.workspace(h, b)
+    V = zeros(64)
+    V64 = zeros(64, torch.float64)
+    st = mb.vi_solve(h, V, b, 101, ws, tol_dv=1e-12, max_sweeps=5000, V64_out=V64)
+    assert st["converged"], st
+    assert np.max(np.abs(V64.cpu().numpy() - Vstar)) <= 1e-11
+    assert np.array_equal(V.cpu().numpy(), V64.cpu().numpy().astype(np.float32))
+
+
+def _trajectory_case(storage):
+    if storage == "dense":
+        P, c = inputs.dense_mdp(1024, 16, 0.1, 2, dtype=np.float32)
+        return dense_case(P, c, 0.99)
+    if storage == "ell":
+        rp, col, val, c = inputs.csr_mdp(3000, 8, 32, 1.0, 3, band=64)
+        return csr_case(rp, col, val, c, 0.995)
+    rp, col, val, c = inputs.csr_ragged_mdp(500, 3, 1, 12, 1.0, 80)
+    return csr_case(rp, col, val, c, 0.95)
+
+
+@pytest.mark.parametrize("storage,b", [("dense", 1024), ("dense", 100), ("dense", 7),
+                                       ("ell", 3000), ("ell", 1000), ("ell", 37),
+                                       ("csr", 500), ("csr", 33)])
+@pytest.mark.parametrize("anchor", [False, True])
+def test_vi_trajectory_matches_oracle(storage, b, anchor):
+    """Several sweeps in one launch against the oracle's MB-VI from the same
+    seeded V0 and orders.  Every sweep boundary is crossed (the first batch
+    of a sweep may hold states of the previous sweep's last batch, all of
+    them when b = n); a lost or stale update there shows up as an error of
+    the size of one sweep's change."""
+    h, mdp = _trajectory_case(storage)
+    n, T = mdp.n, 6
+    mb.mdp_set_tuning(h, recentre_every=(1 if anchor else -1))
+    try:
+        V0 = inputs.values(n, 31, 0.0, 3.0)
+        ws = mb.workspace(h, b)
+        V = up(V0)
+        V64 = zeros(n, torch.float64)
+        st = mb.vi_solve(h, V, b, 55, ws, tol_dv=-1.0, max_sweeps=T, V64_out=V64)
+        assert st["sweeps"] == T
+        ref, _, _ = oracle.value_iteration(mdp, b, 55, V0=V0, tol_dv=-1, max_sweeps=T)
+        scale = float(np.max(np.abs(ref)))
+        assert np.max(np.abs(V64.cpu().numpy() - ref)) <= 1e-5 * scale
+        assert np.max(np.abs(V.cpu().numpy() - ref)) <= 1e-5 * scale
+    finally:
+        mb.mdp_set_tuning(h)
+
+
+@pytest.mark.parametrize("storage,b", [("dense", 1024), ("dense", 100), ("ell", 3000),
+                                       ("ell", 37), ("csr", 33)])
+def test_vi_trajectory_with_recentring_every_sweep(storage, b):
+    """Start next to J* and fold the iterate into the FP64 anchor after every
+    sweep: the trajectory must still be the oracle's (which needs no
+    re-centring in FP64)."""
+    h, mdp = _trajectory_case(storage)
+    n, T = mdp.n, 5
+    Vstar, _, _ = oracle.policy_iteration(mdp)
+    V0 = (Vstar + inputs.values(n, 33, -1e-3, 1e-3, dtype=np.float64)).astype(np.float32)
+    mb.mdp_set_tuning(h, recentre_every=1, recentre_force=1)
+    try:
+        ws = mb.workspace(h, b)
+        V = up(V0)
+        V64 = zeros(n, torch.float64)
+        st = mb.vi_solve(h, V, b, 57, ws, tol_dv=-1.0, max_sweeps=T, V64_out=V64)
+        assert st["recentrings"] == T - 1, st
+        ref, _, _ = oracle.value_iteration(mdp, b, 57, V0=V0, tol_dv=-1, max_sweeps=T)
+        # A lost update or a wrong shift would be as large as the change
+        # itself; FP32 rounding of the first sweep (before the first fold,
+        # on W ~ V0) stays near 1e-7 * max|V|.
+        change = float(np.max(np.abs(ref - V0)))
+        assert np.max(np.abs(V64.cpu().numpy() - ref)) <= 1e-2 * change
+    finally:
+        mb.mdp_set_tuning(h)
+
+
+@pytest.mark.parametrize("storage,b", [("dense", 1024), ("dense", 100), ("ell", 3000),
+                                       ("ell", 37), ("csr", 33)])
+def test_mpi_trajectory_matches_oracle(storage, b):
+    """Three outer iterations of MB-MPI (K = 2) in one launch against the
+    oracle: values and policies after the last improvement."""
+    h, mdp = _trajectory_case(storage)
+    n = mdp.n
+    V0 = inputs.values(n, 32, 0.0, 3.0)
+    ws = mb.workspace(h, b)
+    V = up(V0)
+    pol = torch.zeros(n, dtype=torch.int32, device=dev())
+    st = mb.mpi_solve(h, V, pol, 2, b, 56, ws, policy_is_init=False, tol_dv=-1.0, max_outer=3)
+    assert st["sweeps"] == 6 and st["outer_iters"] == 3
+    ref, mu, _ = oracle.modified_policy_iteration(mdp, 2, b, 56, V0=V0, tol_dv=-1, max_outer=3)
+    scale = float(np.max(np.abs(ref)))
+    assert np.max(np.abs(V.cpu().numpy() - ref)) <= 1e-5 * scale
+    Q = oracle.q_values(mdp, np.arange(n), ref)
+    check_argmin(Q, pol.cpu().numpy(), 1e-5 * scale)
 
 
 def test_vi_resume_reproduces_uninterrupted_run(c1):
@@ -130,12 +233,17 @@ def test_vi_dense_1024x16_reaches_eps(dense_1024, b):
     h, mdp, Vstar = dense_1024
     ws = mb.workspace(h, b)
     V = zeros(1024)
+    V64 = zeros(1024, torch.float64)
     pol = torch.zeros(1024, dtype=torch.int32, device=dev())
     st = mb.vi_solve(h, V, b, 102, ws, tol_dv=-1.0, eps=1e-6, V_ref=up(Vstar),
-                     max_sweeps=4000, policy_out=pol)
+                     max_sweeps=4000, policy_out=pol, V64_out=V64)
     assert st["converged"], st
+    assert np.max(np.abs(V64.cpu().numpy() - Vstar)) <= 1e-6
     assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= out_tol(1e-6, Vstar)
     assert st["recentrings"] >= 1
+    # the same orders in FP64 cross eps within a few sweeps of the GPU
+    _, _, ost = oracle.value_iteration(mdp, b, 102, tol_dv=-1, V_ref=Vstar, eps=1e-6)
+    assert abs(st["sweeps"] - ost.sweeps) <= 3, (st["sweeps"], ost.sweeps)
     assert_optimal_policy(mdp, Vstar, pol.cpu().numpy(), 1e-5 * np.max(np.abs(Vstar)))
 
 

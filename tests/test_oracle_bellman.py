@@ -420,6 +420,37 @@ def test_shifted_costs_give_shifted_iterates(b):
             assert np.array_equal(arg_a, arg_w)
 
 
+@pytest.mark.parametrize("storage", ["dense", "csr"])
+def test_vector_shifted_costs_give_shifted_iterates(storage):
+    """The same exactness with a different shift per state (the form the GPU
+    solvers use: r is the running FP64 anchor of V)."""
+    n, m = 40, 4
+    if storage == "dense":
+        P32 = inputs.dense_dirichlet(n, m, 0.3, 162, dtype=np.float32)
+        mdp = DenseMDP(P32, inputs.costs(n, m, 162).astype(np.float64), 0.99)
+    else:
+        rp, col, val, c = inputs.csr_mdp(n, m, 6, 1.0, 163)
+        mdp = CsrMDP(rp, col, val, c.astype(np.float64), 0.99)
+    V = inputs.values(n, 18, 5, 6, dtype=np.float64)
+    r = inputs.values(n, 19, -3, 9, dtype=np.float64)
+    sh = shifted_costs(mdp, r)
+    shifted = DenseMDP(mdp.P, sh, mdp.gamma) if storage == "dense" else \
+        CsrMDP(mdp.row_ptr, mdp.col, mdp.val, sh, mdp.gamma)
+    for b in (1, 7, 40):
+        for t in range(2):
+            order = sweep_permutation(n, 9, t)
+            a, arg_a, _ = mb_sweep(mdp, V, b, order)
+            w, arg_w, _ = mb_sweep(shifted, V - r, b, order)
+            assert np.allclose(w + r, a, rtol=0, atol=1e-12)
+            assert np.array_equal(arg_a, arg_w)
+            mu = inputs.policy(n, m, 20).astype(np.int64)
+            a2, _, _ = mb_sweep(mdp, V, b, order, policy=mu)
+            w2, _, _ = mb_sweep(shifted, V - r, b, order, policy=mu)
+            assert np.allclose(w2 + r, a2, rtol=0, atol=1e-12)
+    # the scalar form is the vector form with a constant vector
+    assert np.allclose(shifted_costs(mdp, 2.5), shifted_costs(mdp, np.full(n, 2.5)), atol=1e-13)
+
+
 def test_q_values_policy_form_matches_full_form():
     mdp = csr_random(25, 4, 6, 171)
     V = inputs.values(25, 19, dtype=np.float64)
