@@ -121,6 +121,19 @@ __device__ __forceinline__ void wave_argmin(double& q, int& a, int first_off = 1
   }
 }
 
+// The same over the lane bits [FIRST, 64) with constant offsets (unrolled).
+template <int FIRST>
+__device__ __forceinline__ void wave_argmin_from(double& q, int& a) {
+#pragma unroll
+  for (int off = FIRST; off < kWave; off <<= 1) {
+    const double q2 = __shfl_xor(q, off);
+    const int a2 = __shfl_xor(a, off);
+    const bool take = q2 < q || (q2 == q && a2 < a);
+    q = take ? q2 : q;
+    a = take ? a2 : a;
+  }
+}
+
 // Order-preserving 64-bit key of a double (monotone in the value).
 __device__ __forceinline__ unsigned long long okey(double x) {
   const unsigned long long u = (unsigned long long)__double_as_longlong(x);

@@ -123,8 +123,15 @@ struct Ctx {
   float* wr;   // write buffer
 };
 
+// Costs of a row: the solvers always read the FP64 shifted costs (equal to
+// c until the first re-centring), a single sweep reads c itself.  The
+// choice is made at compile time so the hot loops carry no branch for it.
+template <bool CE>
 __device__ __forceinline__ double cost_of(const KParams& p, int64_t row) {
-  return p.ceff ? p.ceff[row] : (double)p.c32[row];
+  if constexpr (CE)
+    return p.ceff[row];
+  else
+    return (double)p.c32[row];
 }
 
 // New value of state s from the FP64 bracket minimum q with action a.  The
@@ -265,6 +272,7 @@ struct DenseEngine {
 
   // Processes this workgroup's units of one batch (ord == nullptr: the
   // states are the positions themselves).
+  template <bool CE, bool IDENT>
   __device__ __forceinline__ static void batch(const KParams& p, const int32_t* ord, int64_t bk,
                                                const Ctx& c, int mode, Local& L) {
     __shared__ float s_sum[16];
@@ -279,7 +287,11 @@ struct DenseEngine {
     for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
       const int64_t i = u / S;
       const int q = (int)(u % S);
-      const int32_t s = ord ? ord[i] : (int32_t)i;
+      int32_t s;
+      if constexpr (IDENT)
+        s = (int32_t)i;
+      else
+        s = ord[i];
       uint32_t j0, j1;
       split_range((uint32_t)n, S, q, j0, j1);
       int apol = (mode == kModePolicy) ? p.policy[s] : 0;
@@ -295,7 +307,7 @@ struct DenseEngine {
         block_sum<1>(acc, s_sum);
         if (threadIdx.x == 0) {
           if (S == 1)
-            s_q[0] = cost_of(p, (int64_t)s * m + apol) + p.gamma * (double)s_sum[0];
+            s_q[0] = cost_of<CE>(p, (int64_t)s * m + apol) + p.gamma * (double)s_sum[0];
           else
             p.partial[(size_t)(i * S + q)] = s_sum[0];
         }
@@ -311,7 +323,7 @@ struct DenseEngine {
           if (threadIdx.x < nrows) {
             const int a = a0 + threadIdx.x;
             if (S == 1)
-              s_q[a] = cost_of(p, (int64_t)s * m + a) + p.gamma * (double)s_sum[threadIdx.x];
+              s_q[a] = cost_of<CE>(p, (int64_t)s * m + a) + p.gamma * (double)s_sum[threadIdx.x];
             else
               p.partial[(size_t)(i * S + q) * m + a] = s_sum[threadIdx.x];
           }
@@ -336,7 +348,7 @@ struct DenseEngine {
           double sum = 0.0;
           for (int qq = 0; qq < S; ++qq) sum += (double)p.partial[(size_t)(i * S + qq) * mr + a];
           const int act = (mode == kModePolicy) ? apol : a;
-          s_q[a] = cost_of(p, (int64_t)s * m + act) + p.gamma * sum;
+          s_q[a] = cost_of<CE>(p, (int64_t)s * m + act) + p.gamma * sum;
         }
       }
       __syncthreads();
@@ -405,26 +417,29 @@ struct DenseEngine {
 // Constant row length k, k % 4 == 0, k <= 256.  A row is served by LPR =
 // (k/4 rounded up to a power of two) lanes; a wavefront covers RPP = 64/LPR
 // rows per pass.  In the minimum modes a wavefront serves UNR states at a
-// time; in the policy mode each lane group serves its own state.
-template <int UNR>
+// time; in the policy mode each lane group serves its own state.  LPR is a
+// template parameter so that the lane reductions unroll with constant
+// shuffle offsets.
+template <int UNR, int LPR>
 struct EllEngine {
-  __device__ __forceinline__ static int lanes_per_row(int k) {
-    int lpr = 1;
-    while (lpr * 4 < k) lpr <<= 1;
-    return lpr;
-  }
 
   // One wavefront iteration serves UNR states (min modes) or UNR lane
   // groups of states (policy mode).  The states of the next iteration are
   // fetched one iteration ahead, and the costs and old values are loaded
   // together with the columns and weights, so an iteration waits for two
-  // round trips (the row stream, then the V gathers).
+  // round trips (the row stream, then the V gathers).  Every load uses a
+  // valid address (positions past the batch end read state 0, lanes beyond a
+  // row read the row's first entries, rows past m read row m-1) and unused
+  // results are discarded by selects, so the loads issue back to back
+  // without branches.
+  template <bool CE, bool IDENT>
   __device__ __forceinline__ static void batch(const KParams& p, const int32_t* ord, int64_t bk,
                                                const Ctx& c, int mode, Local& L) {
     const int m = p.m, k = p.ell_k;
-    const int lpr = lanes_per_row(k), rpp = kWave / lpr;
+    constexpr int lpr = LPR, rpp = kWave / LPR;
     const int lane = threadIdx.x & 63, g = lane / lpr, l = lane % lpr;
     const bool lane_has_data = l * 4 < k;
+    const int lcol = lane_has_data ? l * 4 : 0;
     const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
     const bool improve = mode >= kModeImprove;
@@ -432,20 +447,31 @@ struct EllEngine {
     // positions of a unit: min modes UNR states, policy mode UNR groups of rpp
     const int64_t per_unit = pol ? (int64_t)rpp * UNR : (int64_t)UNR;
     const int64_t units = (bk + per_unit - 1) / per_unit;
+    // state at slot x of unit u, or -1 past the batch end
     auto state_at = [&](int64_t u, int x) -> int32_t {
       const int64_t pos = pol ? u * per_unit + (int64_t)x * rpp + g : u * per_unit + x;
-      return (u < units && pos < bk) ? (ord ? ord[pos] : (int32_t)pos) : -1;
+      const bool valid = u < units && pos < bk;
+      const int64_t pc = valid ? pos : 0;
+      int32_t v;
+      if constexpr (IDENT)
+        v = (int32_t)pc;
+      else
+        v = ord[pc];
+      return valid ? v : -1;
     };
+    const float* __restrict__ rd = c.rd;
     int32_t s_next[UNR];
 #pragma unroll
     for (int x = 0; x < UNR; ++x) s_next[x] = state_at(gw, x);
     for (int64_t u = gw; u < units; u += nw) {
-      int32_t s[UNR];
-#pragma unroll
-      for (int x = 0; x < UNR; ++x) s[x] = s_next[x];
+      int32_t s[UNR], sc[UNR];
       float old[UNR];
 #pragma unroll
-      for (int x = 0; x < UNR; ++x) old[x] = s[x] >= 0 ? c.rd[s[x]] : 0.f;
+      for (int x = 0; x < UNR; ++x) {
+        s[x] = s_next[x];
+        sc[x] = s[x] >= 0 ? s[x] : 0;
+        old[x] = rd[sc[x]];
+      }
       if (pol) {
         int a[UNR];
         i4 cc[UNR];
@@ -453,28 +479,32 @@ struct EllEngine {
         double cost[UNR];
 #pragma unroll
         for (int x = 0; x < UNR; ++x) {
-          a[x] = s[x] >= 0 ? p.policy[s[x]] : 0;
-          if (a[x] < 0 || a[x] >= m) {
-            raise_abort(p.ctl, kDevBadPolicy);
-            a[x] = 0;
+          int av = p.policy[sc[x]];
+          if (av < 0 || av >= m) {
+            if (s[x] >= 0) raise_abort(p.ctl, kDevBadPolicy);
+            av = 0;
           }
-          const bool ok = s[x] >= 0 && lane_has_data;
-          const size_t e = ((size_t)(ok ? s[x] : 0) * m + a[x]) * (size_t)k + (size_t)l * 4;
-          cc[x] = ok ? __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e))
-                     : i4{0, 0, 0, 0};
-          vv[x] = ok ? __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e))
-                     : f4{0.f, 0.f, 0.f, 0.f};
-          cost[x] = s[x] >= 0 ? cost_of(p, (int64_t)s[x] * m + a[x]) : 0.0;
+          a[x] = av;
+          const size_t e = ((size_t)sc[x] * m + av) * (size_t)k + (size_t)lcol;
+          cc[x] = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e));
+          vv[x] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e));
+          cost[x] = cost_of<CE>(p, (int64_t)sc[x] * m + av);
         }
 #pragma unroll
         for (int x = 0; x < UNR; ++x) s_next[x] = state_at(u + nw, x);
+        f4 gv[UNR];  // all V gathers of the iteration are issued before any use
+#pragma unroll
+        for (int x = 0; x < UNR; ++x)
+          gv[x] = f4{rd[cc[x].x], rd[cc[x].y], rd[cc[x].z], rd[cc[x].w]};
 #pragma unroll
         for (int x = 0; x < UNR; ++x) {
-          float part = vv[x].x * c.rd[cc[x].x];
-          part = fmaf(vv[x].y, c.rd[cc[x].y], part);
-          part = fmaf(vv[x].z, c.rd[cc[x].z], part);
-          part = fmaf(vv[x].w, c.rd[cc[x].w], part);
-          for (int off = lpr >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
+          float part = vv[x].x * gv[x].x;
+          part = fmaf(vv[x].y, gv[x].y, part);
+          part = fmaf(vv[x].z, gv[x].z, part);
+          part = fmaf(vv[x].w, gv[x].w, part);
+          part = lane_has_data ? part : 0.f;
+          #pragma unroll
+          for (int off = LPR >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
           if (l == 0 && s[x] >= 0)
             commit_sweep(p, c, s[x], cost[x] + p.gamma * (double)part, a[x], old[x], L);
         }
@@ -487,46 +517,44 @@ struct EllEngine {
         qb[x] = INFINITY;
         ab[x] = 0x7fffffff;
       }
-      bool prefetched = false;
       for (int a0 = 0; a0 < m; a0 += rpp) {
         const int a = a0 + g;
-        const bool row_ok = a < m && lane_has_data;
+        const bool row_ok = a < m;
+        const int ac = row_ok ? a : m - 1;
         i4 cc[UNR];
         f4 vv[UNR];
         double cost[UNR];
 #pragma unroll
         for (int x = 0; x < UNR; ++x) {
-          const bool ok = row_ok && s[x] >= 0;
-          const size_t e = ((size_t)(ok ? s[x] : 0) * m + a) * (size_t)k + (size_t)l * 4;
-          cc[x] = ok ? __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e))
-                     : i4{0, 0, 0, 0};
-          vv[x] = ok ? __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e))
-                     : f4{0.f, 0.f, 0.f, 0.f};
-          cost[x] = (a < m && s[x] >= 0) ? cost_of(p, (int64_t)s[x] * m + a) : INFINITY;
+          const size_t e = ((size_t)sc[x] * m + ac) * (size_t)k + (size_t)lcol;
+          cc[x] = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e));
+          vv[x] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e));
+          cost[x] = cost_of<CE>(p, (int64_t)sc[x] * m + ac);
         }
-        if (!prefetched) {
+        if (a0 == 0) {
 #pragma unroll
           for (int x = 0; x < UNR; ++x) s_next[x] = state_at(u + nw, x);
-          prefetched = true;
         }
+        f4 gv[UNR];  // all V gathers of the iteration are issued before any use
+#pragma unroll
+        for (int x = 0; x < UNR; ++x)
+          gv[x] = f4{rd[cc[x].x], rd[cc[x].y], rd[cc[x].z], rd[cc[x].w]};
 #pragma unroll
         for (int x = 0; x < UNR; ++x) {
-          float part = vv[x].x * c.rd[cc[x].x];
-          part = fmaf(vv[x].y, c.rd[cc[x].y], part);
-          part = fmaf(vv[x].z, c.rd[cc[x].z], part);
-          part = fmaf(vv[x].w, c.rd[cc[x].w], part);
-          for (int off = lpr >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
-          double q = INFINITY;
-          int aq = 0x7fffffff;
-          if (a < m && s[x] >= 0) {
-            q = cost[x] + p.gamma * (double)part;
-            aq = a;
-          }
-          wave_argmin(q, aq, lpr);
-          if (q < qb[x] || (q == qb[x] && aq < ab[x])) {
-            qb[x] = q;
-            ab[x] = aq;
-          }
+          float part = vv[x].x * gv[x].x;
+          part = fmaf(vv[x].y, gv[x].y, part);
+          part = fmaf(vv[x].z, gv[x].z, part);
+          part = fmaf(vv[x].w, gv[x].w, part);
+          part = lane_has_data ? part : 0.f;
+          #pragma unroll
+          for (int off = LPR >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
+          const bool use = row_ok && s[x] >= 0;
+          double q = use ? cost[x] + p.gamma * (double)part : INFINITY;
+          int aq = use ? a : 0x7fffffff;
+          wave_argmin_from<LPR>(q, aq);
+          const bool better = q < qb[x] || (q == qb[x] && aq < ab[x]);
+          qb[x] = better ? q : qb[x];
+          ab[x] = better ? aq : ab[x];
         }
       }
       if (lane == 0) {
@@ -546,7 +574,7 @@ struct EllEngine {
   // c'(s,a) = c(s,a) - R(s) + gamma * (P R)(s,a) in FP64, a wavefront per state.
   __device__ __forceinline__ static void shift_costs(const KParams& p) {
     const int m = p.m, k = p.ell_k;
-    const int lpr = lanes_per_row(k), rpp = kWave / lpr;
+    constexpr int lpr = LPR, rpp = kWave / LPR;
     const int lane = threadIdx.x & 63, g = lane / lpr, l = lane % lpr;
     const bool lane_has_data = l * 4 < k;
     const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -563,7 +591,8 @@ struct EllEngine {
           part = (double)vv.x * p.shift[cc.x] + (double)vv.y * p.shift[cc.y] +
                  (double)vv.z * p.shift[cc.z] + (double)vv.w * p.shift[cc.w];
         }
-        for (int off = lpr >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
+        #pragma unroll
+          for (int off = LPR >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
         if (l == 0 && a < m) {
           const int64_t row = s * m + a;
           p.ceff[row] = (double)p.c32[row] - rs + p.gamma * part;
@@ -576,6 +605,7 @@ struct EllEngine {
 // ------------------------------------------------------------ general CSR engine
 
 struct CsrEngine {
+  template <bool CE, bool IDENT>
   __device__ __forceinline__ static void batch(const KParams& p, const int32_t* ord, int64_t bk,
                                                const Ctx& c, int mode, Local& L) {
     const int m = p.m;
@@ -584,7 +614,11 @@ struct CsrEngine {
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
     const bool improve = mode >= kModeImprove;
     for (int64_t u = gw; u < bk; u += nw) {
-      const int32_t s = ord ? ord[u] : (int32_t)u;
+      int32_t s;
+      if constexpr (IDENT)
+        s = (int32_t)u;
+      else
+        s = ord[u];
       double qb = INFINITY;
       int ab = 0x7fffffff;
       int a_lo = mode == kModePolicy ? p.policy[s] : 0;
@@ -600,7 +634,7 @@ struct CsrEngine {
         for (int64_t e = e0 + lane; e < e1; e += kWave)
           part = fmaf(__builtin_nontemporal_load(p.val + e), c.rd[p.col[e]], part);
         part = wave_sum(part);
-        const double q = cost_of(p, row) + p.gamma * (double)part;
+        const double q = cost_of<CE>(p, row) + p.gamma * (double)part;
         if (q < qb) {
           qb = q;
           ab = a;
@@ -705,7 +739,7 @@ struct Driver {
 
   __device__ __forceinline__ int slot() const { return (int)(epoch % 3); }
 
-  template <class Eng>
+  template <class Eng, bool CE>
   __device__ __forceinline__ bool sweep(uint64_t t, int mode) {
     const int64_t n = p.n, b = p.b, nb = (n + b - 1) / b;
     if (blockIdx.x == 0 && threadIdx.x == 0) reset_slot(p.ctl, (int)((epoch + 1) % 3));
@@ -725,7 +759,7 @@ struct Driver {
         fill_order(t, kb + b, min(b, n - kb - b));
       else
         fill_order(t + 1, 0, min(b, n));
-      Eng::batch(p, ord + kb, bk, c, mode, L);
+      Eng::template batch<CE, false>(p, ord + kb, bk, c, mode, L);
       prev_order = ord + kb;
       prev_count = bk;
       if (k == nb - 1) flush_local(L, p.ctl, slot());
@@ -736,11 +770,11 @@ struct Driver {
     return true;
   }
 
-  template <class Eng>
+  template <class Eng, bool CE>
   __device__ __forceinline__ bool improve(bool count) {
     if (blockIdx.x == 0 && threadIdx.x == 0) reset_slot(p.ctl, (int)((epoch + 1) % 3));
     Ctx c{rd_buf(), wr_buf()};
-    Eng::batch(p, nullptr, p.n, c, count ? kModeImproveCount : kModeImprove, L);
+    Eng::template batch<CE, true>(p, nullptr, p.n, c, count ? kModeImproveCount : kModeImprove, L);
     flush_local(L, p.ctl, slot());
     if (!grid_sync(g)) return false;
     ++epoch;
@@ -813,15 +847,19 @@ struct Driver {
   }
 };
 
+// One 1024-thread workgroup per CU is 4 waves per SIMD: let the compiler use
+// the 128 VGPRs that allows rather than serialise loads for occupancy.
 template <class Eng, int TASK>
-__global__ void __launch_bounds__(1024) solve_kernel(KParams p) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)))
+solve_kernel(KParams p) {
   Driver d(p);
   const int64_t n = p.n;
   uint64_t t = p.first_sweep;
   // prologue: second buffer, row sums and shifted costs, first order
   for (int64_t s = d.gtid; s < n; s += d.gthreads) p.vbuf1[s] = p.vbuf0[s];
-  if (TASK != kTaskSweep && p.recentre_every > 0) {
-    for (int64_t s = d.gtid; s < n; s += d.gthreads) p.shift[s] = 0.0;
+  if (TASK != kTaskSweep) {
+    if (p.shift)
+      for (int64_t s = d.gtid; s < n; s += d.gthreads) p.shift[s] = 0.0;
     for (int64_t i = d.gtid; i < n * p.m; i += d.gthreads) p.ceff[i] = (double)p.c32[i];
   }
   long long since_recentre = 0;
@@ -834,13 +872,13 @@ __global__ void __launch_bounds__(1024) solve_kernel(KParams p) {
   int converged = 0;
 
   if constexpr (TASK == kTaskSweep) {
-    if (!d.template sweep<Eng>(t, p.policy_sweep ? kModePolicy : kModeMin)) return;
+    if (!d.template sweep<Eng, false>(t, p.policy_sweep ? kModePolicy : kModeMin)) return;
     sweeps = 1;
     last_dv = slot_double(p.ctl, (int)((d.epoch - 1) % 3), kAccDv);
     converged = 1;
   } else if constexpr (TASK == kTaskVI) {
     while (true) {
-      if (!d.template sweep<Eng>(t, kModeMin)) return;
+      if (!d.template sweep<Eng, true>(t, kModeMin)) return;
       ++t;
       ++sweeps;
       const int sl = (int)((d.epoch - 1) % 3);
@@ -861,14 +899,14 @@ __global__ void __launch_bounds__(1024) solve_kernel(KParams p) {
       }
     }
     if (p.want_policy_out)
-      if (!d.template improve<Eng>(false)) return;
+      if (!d.template improve<Eng, true>(false)) return;
   } else {  // MPI, Algorithm 1
     if (!p.policy_is_init)
-      if (!d.template improve<Eng>(false)) return;
+      if (!d.template improve<Eng, true>(false)) return;
     bool done = false;
     while (!done) {
       for (int k = 0; k < p.K; ++k) {
-        if (!d.template sweep<Eng>(t, kModePolicy)) return;
+        if (!d.template sweep<Eng, true>(t, kModePolicy)) return;
         ++t;
         ++sweeps;
         const int sl = (int)((d.epoch - 1) % 3);
@@ -886,7 +924,7 @@ __global__ void __launch_bounds__(1024) solve_kernel(KParams p) {
         }
       }
       if (done) break;
-      if (!d.template improve<Eng>(true)) return;
+      if (!d.template improve<Eng, true>(true)) return;
       ++outer;
       const int sl = (int)((d.epoch - 1) % 3);
       changes_last = (long long)atomic_load_agent(&p.ctl->acc[sl][kAccChanges]);
@@ -1034,8 +1072,18 @@ static SolveFn pick(const KParams& p, int units_per_wave_hint) {
   }
   if (p.storage == kEll) {
     // two states per wavefront iteration keep the pipelined loop within 128 VGPRs
-    if (units_per_wave_hint >= 2) return solve_fn<EllEngine<2>>(p.task);
-    return solve_fn<EllEngine<1>>(p.task);
+    int lpr = 1;
+    while (lpr * 4 < p.ell_k) lpr <<= 1;
+    const bool two = units_per_wave_hint >= 2;
+    switch (lpr) {
+      case 1: return two ? solve_fn<EllEngine<2, 1>>(p.task) : solve_fn<EllEngine<1, 1>>(p.task);
+      case 2: return two ? solve_fn<EllEngine<2, 2>>(p.task) : solve_fn<EllEngine<1, 2>>(p.task);
+      case 4: return two ? solve_fn<EllEngine<2, 4>>(p.task) : solve_fn<EllEngine<1, 4>>(p.task);
+      case 8: return two ? solve_fn<EllEngine<2, 8>>(p.task) : solve_fn<EllEngine<1, 8>>(p.task);
+      case 16: return two ? solve_fn<EllEngine<2, 16>>(p.task) : solve_fn<EllEngine<1, 16>>(p.task);
+      case 32: return two ? solve_fn<EllEngine<2, 32>>(p.task) : solve_fn<EllEngine<1, 32>>(p.task);
+      default: return two ? solve_fn<EllEngine<2, 64>>(p.task) : solve_fn<EllEngine<1, 64>>(p.task);
+    }
   }
   return solve_fn<CsrEngine>(p.task);
 }

@@ -413,10 +413,9 @@ mbdp_status vi_solve(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy_ou
   p.max_sweeps = max_sweeps;
   p.recentre_every = recentre_interval(h);
   p.recentre_force = h->tuning.recentre_force != 0;
-  if (p.recentre_every > 0) {
-    p.ceff = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.ceff);
+  p.ceff = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.ceff);
+  if (p.recentre_every > 0)
     p.shift = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.shift);
-  }
   st = launch(h, p, workspace, stream);
   if (st != MBDP_OK) return st;
   Control c;
@@ -460,10 +459,9 @@ mbdp_status mpi_solve(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy,
   p.max_outer = max_outer;
   p.recentre_every = recentre_interval(h);
   p.recentre_force = h->tuning.recentre_force != 0;
-  if (p.recentre_every > 0) {
-    p.ceff = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.ceff);
+  p.ceff = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.ceff);
+  if (p.recentre_every > 0)
     p.shift = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.shift);
-  }
   st = launch(h, p, workspace, stream);
   if (st != MBDP_OK) return st;
   Control c;
