@@ -90,6 +90,9 @@ typedef struct {
   int32_t recentre_every;      /* solvers: minimum sweeps between re-centrings; -1 disables */
   int32_t recentre_force;      /* nonzero: re-centre after every recentre_every sweeps
                                   whatever the size of the change (testing) */
+  int32_t band_window;         /* constant-row-length sparse MDPs whose columns stay in a
+                                  band around their state: 0 stages the band of V in LDS
+                                  when it fits, -1 never does (V is gathered from memory) */
 } mbdp_tuning;
 
 /* Dense MDP (P as in Sec. II-A, stored [n][m][n]).  Records the pointers;
@@ -115,6 +118,15 @@ mbdp_status mdp_set_tuning(mbdp_mdp_t h, const mbdp_tuning* t);
 /* Workspace bytes that mb_sweep, vi_solve, mpi_solve and mdp_validate need
  * for this handle with batch size b (0 on a bad handle or batch size). */
 size_t mdp_workspace_bytes(mbdp_mdp_t h, int64_t b);
+
+/* Name of the kernel family that mb_sweep (without an explicit order),
+ * vi_solve and mpi_solve run for this handle and batch size b: "dense",
+ * "ell" (constant row length, V gathered from memory), "ell-band" (constant
+ * row length with every column within a band around its state: each
+ * workgroup owns a chunk of states and stages the band of V it reads in
+ * LDS) or "csr".  The choice follows the handle's tuning.  *name points to
+ * a static string.  No device work. */
+mbdp_status mdp_engine(mbdp_mdp_t h, int64_t b, const char** name);
 
 /* Optional input checks: P entries in [0, inf), FP64 row sums within
  * row_sum_tol of 1, CSR structure, costs not NaN/-inf and at least one

@@ -31,7 +31,7 @@ STATUS_NAMES = {
 # Every symbol include/mbdp.h declares.
 EXPORTS = [
     "mdp_create_dense", "mdp_create_csr", "mdp_destroy", "mdp_set_tuning",
-    "mdp_workspace_bytes", "mdp_validate", "mbdp_permutation", "mb_sweep",
+    "mdp_workspace_bytes", "mdp_engine", "mdp_validate", "mbdp_permutation", "mb_sweep",
     "mbdp_sync_status", "vi_solve", "mpi_solve", "mbdp_last_error",
 ]
 
@@ -69,7 +69,8 @@ class Validation(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_int32), ("threads_per_block", ctypes.c_int32),
-                ("recentre_every", ctypes.c_int32), ("recentre_force", ctypes.c_int32)]
+                ("recentre_every", ctypes.c_int32), ("recentre_force", ctypes.c_int32),
+                ("band_window", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -83,6 +84,7 @@ _SIGS = {
     "mdp_destroy": (_I32, [_P]),
     "mdp_set_tuning": (_I32, [_P, ctypes.POINTER(Tuning)]),
     "mdp_workspace_bytes": (ctypes.c_size_t, [_P, _I64]),
+    "mdp_engine": (_I32, [_P, _I64, ctypes.POINTER(ctypes.c_char_p)]),
     "mdp_validate": (_I32, [_P, _D, _P, ctypes.c_size_t, _P, ctypes.POINTER(Validation)]),
     "mbdp_permutation": (_I32, [_I64, _U64, _U64, _P, _P]),
     "mb_sweep": (_I32, [_P, _P, _P, _I64, _U64, _U64, _P, _P, _P, _P, ctypes.c_size_t, _P]),
@@ -196,9 +198,18 @@ def mdp_destroy(h):
     h.close()
 
 
-def mdp_set_tuning(h, blocks_per_cu=0, threads_per_block=0, recentre_every=0, recentre_force=0):
-    t = Tuning(blocks_per_cu, threads_per_block, recentre_every, int(bool(recentre_force)))
+def mdp_set_tuning(h, blocks_per_cu=0, threads_per_block=0, recentre_every=0, recentre_force=0,
+                   band_window=0):
+    t = Tuning(blocks_per_cu, threads_per_block, recentre_every, int(bool(recentre_force)),
+               band_window)
     _check(lib().mdp_set_tuning(h.ptr, ctypes.byref(t)))
+
+
+def mdp_engine(h, b):
+    """Kernel family the solvers run for this handle and batch size."""
+    name = ctypes.c_char_p()
+    _check(lib().mdp_engine(h.ptr, int(b), ctypes.byref(name)))
+    return name.value.decode()
 
 
 def mdp_workspace_bytes(h, b):

@@ -82,6 +82,27 @@ __device__ __forceinline__ uint32_t sweep_order_at(uint32_t p, const OrderKey& k
   return y;
 }
 
+// The network run backwards: round j maps (L, R) to (R ^ f_j(L), L).
+__device__ __forceinline__ uint32_t feistel_inverse(uint32_t y, const OrderKey& k) {
+  uint32_t left = y >> k.h, right = y & k.mask;
+#pragma unroll
+  for (int j = 3; j >= 0; --j) {
+    const uint32_t f = philox_word0(left, (uint32_t)j, k.t_lo, k.t_hi, k.s_lo, k.s_hi) & k.mask;
+    const uint32_t prev_left = right ^ f;
+    right = left;
+    left = prev_left;
+  }
+  return (left << k.h) | right;
+}
+
+// Position of state s in the order of sweep t, sigma_t^{-1}(s): cycle walking
+// backwards through the values outside [0, n).
+__device__ __forceinline__ uint32_t sweep_position_of(uint32_t s, const OrderKey& k) {
+  uint32_t x = feistel_inverse(s, k);
+  while (x >= k.n) x = feistel_inverse(x, k);
+  return x;
+}
+
 // ------------------------------------------------------------ reductions
 
 __device__ __forceinline__ float wave_sum(float v) {

@@ -64,7 +64,7 @@ struct KParams {
   const int32_t* col;
   const float* val;
   int32_t ell_k;           // constant row length (kEll), else 0
-  int32_t pad0;
+  int32_t band;            // kEll: max |s' - s| over the entries of state s's rows; -1 unknown or off
   const float* c32;        // plain costs [n*m]
   double* ceff;            // shifted costs [n*m] (solvers), workspace
   double* shift;           // FP64 anchor R[n] with V = W + R (solvers), workspace
@@ -142,9 +142,14 @@ struct LaunchShape {
 
 constexpr int kMaxBlocksPerCu = 16;
 
+// Kernel families a launch can run.
+enum Engine : int { kEngineDense = 0, kEngineEll = 1, kEngineBand = 2, kEngineCsr = 3 };
+
 // Fills p.splits from the grid actually used and launches the persistent
 // kernel cooperatively.  Returns 0 or -1 with a message in err.
 int launch_solve(KParams p, LaunchShape shape, void* stream, char* err, size_t errlen);
+// The kernel family launch_solve would run for p (no device work).
+int query_engine(const KParams& p, LaunchShape shape, int* engine, char* err, size_t errlen);
 int launch_zero(void* ptr, size_t bytes, void* stream);
 int launch_permutation(int64_t n, uint64_t seed, uint64_t t, int32_t* out, void* stream);
 int launch_csr_inspect(const int64_t* row_ptr, const int32_t* col, int64_t rows, int64_t n,

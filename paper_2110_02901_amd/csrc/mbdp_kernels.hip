@@ -255,6 +255,8 @@ constexpr int kMaxActions = 1024;
 
 template <int R, int VEC>
 struct DenseEngine {
+  static constexpr bool kBand = false;
+
   // Column range of split q of S, rounded to whole block-wide vector steps.
   __device__ __forceinline__ static void split_range(uint32_t n, int S, int q, uint32_t& j0,
                                                      uint32_t& j1) {
@@ -422,6 +424,8 @@ struct DenseEngine {
 // shuffle offsets.
 template <int UNR, int LPR>
 struct EllEngine {
+  static constexpr bool kBand = false;
+
 
   // One wavefront iteration serves UNR states (min modes) or UNR lane
   // groups of states (policy mode).  The states of the next iteration are
@@ -602,9 +606,242 @@ struct EllEngine {
   }
 };
 
+// ------------------------------------------------------------ band-local ELL engine
+//
+// When every column of the rows of state s lies within a band |s' - s| <=
+// beta, workgroup w owns one contiguous chunk of D states and computes, in
+// each batch, exactly the states of the batch that fall in its chunk.  Their
+// reads stay inside the window [w D - beta, (w+1) D + beta) of V, which the
+// workgroup copies into LDS with coalesced loads at the start of the batch,
+// so the k reads per row are LDS reads instead of scattered memory reads.
+// A batch is a set of states that all read the values from before the batch
+// (eq. (11)), so the order inside it is free: at the start of a sweep the
+// workgroup sorts its chunk by batch index sigma_t^{-1}(s) / b (the Feistel
+// network run backwards) with a counting sort in LDS, and batch k is then
+// one contiguous run of that list.
+constexpr int kWinCap = 16384;   // V entries staged in LDS (64 KB)
+constexpr int kChunkCap = 8192;  // states of one workgroup's chunk
+constexpr int kBatchCap = 4096;  // batches per sweep
+
+struct BandShared {
+  float win[kWinCap];               // V[wlo, wlo + wn) of the current batch; sort scratch
+  uint16_t lst[2][kChunkCap];       // chunk offsets ordered by batch, by sweep parity
+  int32_t off[kBatchCap + 1];       // batch k is lst[.][off[k], off[k+1])
+  uint32_t first0[kChunkCap / 32];  // bit i: state c0 + i is in batch 0 of the newest sweep
+  int32_t wsum[16];                 // per-wave partial sums of the scan
+};
+
+__device__ __forceinline__ BandShared& band_shared() {
+  __shared__ BandShared sh;
+  return sh;
+}
+
+struct BandGeom {
+  int64_t c0;   // first state of the chunk
+  int dw;       // states in the chunk
+  int64_t wlo;  // first V entry of the window
+  int wn;       // entries in the window
+};
+
+__device__ __forceinline__ BandGeom band_geom(const KParams& p) {
+  const int64_t D = (p.n + gridDim.x - 1) / gridDim.x;
+  BandGeom g;
+  g.c0 = min(p.n, (int64_t)blockIdx.x * D);
+  const int64_t c1 = min(p.n, g.c0 + D);
+  g.dw = (int)(c1 - g.c0);
+  g.wlo = max((int64_t)0, g.c0 - (int64_t)p.band);
+  g.wn = g.dw > 0 ? (int)(min(p.n, c1 + (int64_t)p.band) - g.wlo) : 0;
+  return g;
+}
+
+// a[0, cnt) <- its exclusive prefix sums, in place, over the workgroup.
+__device__ __forceinline__ void block_exclusive_scan(int32_t* a, int cnt, int32_t* wsum) {
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, w = tid >> 6;
+  const int per = (cnt + nt - 1) / nt;
+  const int i0 = min(cnt, tid * per), i1 = min(cnt, i0 + per);
+  int sum = 0;
+  for (int i = i0; i < i1; ++i) sum += a[i];
+  int x = sum;  // inclusive scan over the wavefront
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) wsum[w] = x;
+  __syncthreads();
+  int run = x - sum;
+  for (int j = 0; j < w; ++j) run += wsum[j];
+  for (int i = i0; i < i1; ++i) {
+    const int v = a[i];
+    a[i] = run;
+    run += v;
+  }
+  __syncthreads();
+}
+
+// lst[buf] <- the chunk's offsets ordered by batch of sweep t; off, first0.
+__device__ __forceinline__ void band_sort(const KParams& p, BandShared& sh, const BandGeom& bg,
+                                          uint64_t t, int buf, int nb) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i <= nb; i += nt) sh.off[i] = 0;
+  for (int i = tid; i < (bg.dw + 31) / 32; i += nt) sh.first0[i] = 0u;
+  __syncthreads();
+  uint32_t* kr = reinterpret_cast<uint32_t*>(sh.win);  // (batch << 16) | rank in batch
+  const OrderKey key = make_order_key(p.n, p.seed, t);
+  const uint32_t b = (uint32_t)p.b;
+  for (int i = tid; i < bg.dw; i += nt) {
+    const uint32_t kb = sweep_position_of((uint32_t)(bg.c0 + i), key) / b;
+    const uint32_t r = (uint32_t)atomicAdd(&sh.off[kb], 1);
+    kr[i] = (kb << 16) | r;
+  }
+  __syncthreads();
+  block_exclusive_scan(sh.off, nb, sh.wsum);
+  if (tid == 0) sh.off[nb] = bg.dw;
+  __syncthreads();
+  for (int i = tid; i < bg.dw; i += nt) {
+    const uint32_t v = kr[i];
+    const uint32_t kb = v >> 16;
+    sh.lst[buf][sh.off[kb] + (int)(v & 0xFFFFu)] = (uint16_t)i;
+    if (kb == 0) atomicOr(&sh.first0[i >> 5], 1u << (i & 31));
+  }
+  __syncthreads();
+}
+
+// The ELL loop of EllEngine with state ids from the workgroup's list and V
+// read from the window in LDS.  Row streams, costs and policies still come
+// from memory; the recentring pass (shift_costs) is EllEngine's.
+template <int UNR, int LPR>
+struct BandEngine : EllEngine<UNR, LPR> {
+  static constexpr bool kBand = true;
+
+  template <bool CE, bool IDENT>
+  __device__ __forceinline__ static void batch_band(const KParams& p, const BandShared& sh,
+                                                    const uint16_t* lst, int cnt,
+                                                    const BandGeom& bg, const Ctx& c, int mode,
+                                                    Local& L) {
+    const int m = p.m, k = p.ell_k;
+    constexpr int rpp = kWave / LPR;
+    const int lane = threadIdx.x & 63, g = lane / LPR, l = lane % LPR;
+    const bool lane_has_data = l * 4 < k;
+    const int lcol = lane_has_data ? l * 4 : 0;
+    const int wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+    const bool improve = mode >= kModeImprove;
+    const bool pol = mode == kModePolicy;
+    const int per_unit = pol ? rpp * UNR : UNR;
+    const int units = (cnt + per_unit - 1) / per_unit;
+    const float* win = sh.win;
+    const int32_t wlo = (int32_t)bg.wlo;
+    const uint32_t wlast = (uint32_t)(bg.wn > 0 ? bg.wn - 1 : 0);
+    // V(j) from the window; the clamp only keeps an index inside the array
+    auto at = [&](int32_t j) -> float { return win[min((uint32_t)(j - wlo), wlast)]; };
+    for (int u = wv; u < units; u += nwv) {
+      int32_t s[UNR], sc[UNR];
+      float old[UNR];
+#pragma unroll
+      for (int x = 0; x < UNR; ++x) {
+        const int pos = pol ? u * per_unit + x * rpp + g : u * per_unit + x;
+        const bool valid = pos < cnt;
+        const int pc = valid ? pos : 0;
+        int o;
+        if constexpr (IDENT)
+          o = pc;
+        else
+          o = (int)lst[pc];
+        sc[x] = (int32_t)bg.c0 + o;
+        s[x] = valid ? sc[x] : -1;
+        old[x] = at(sc[x]);
+      }
+      if (pol) {
+        int a[UNR];
+        i4 cc[UNR];
+        f4 vv[UNR];
+        double cost[UNR];
+#pragma unroll
+        for (int x = 0; x < UNR; ++x) {
+          int av = p.policy[sc[x]];
+          if (av < 0 || av >= m) {
+            if (s[x] >= 0) raise_abort(p.ctl, kDevBadPolicy);
+            av = 0;
+          }
+          a[x] = av;
+          const size_t e = ((size_t)sc[x] * m + av) * (size_t)k + (size_t)lcol;
+          cc[x] = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e));
+          vv[x] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e));
+          cost[x] = cost_of<CE>(p, (int64_t)sc[x] * m + av);
+        }
+#pragma unroll
+        for (int x = 0; x < UNR; ++x) {
+          float part = vv[x].x * at(cc[x].x);
+          part = fmaf(vv[x].y, at(cc[x].y), part);
+          part = fmaf(vv[x].z, at(cc[x].z), part);
+          part = fmaf(vv[x].w, at(cc[x].w), part);
+          part = lane_has_data ? part : 0.f;
+#pragma unroll
+          for (int off = LPR >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
+          if (l == 0 && s[x] >= 0)
+            commit_sweep(p, c, s[x], cost[x] + p.gamma * (double)part, a[x], old[x], L);
+        }
+        continue;
+      }
+      double qb[UNR];
+      int ab[UNR];
+#pragma unroll
+      for (int x = 0; x < UNR; ++x) {
+        qb[x] = INFINITY;
+        ab[x] = 0x7fffffff;
+      }
+      for (int a0 = 0; a0 < m; a0 += rpp) {
+        const int a = a0 + g;
+        const bool row_ok = a < m;
+        const int ac = row_ok ? a : m - 1;
+        i4 cc[UNR];
+        f4 vv[UNR];
+        double cost[UNR];
+#pragma unroll
+        for (int x = 0; x < UNR; ++x) {
+          const size_t e = ((size_t)sc[x] * m + ac) * (size_t)k + (size_t)lcol;
+          cc[x] = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e));
+          vv[x] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e));
+          cost[x] = cost_of<CE>(p, (int64_t)sc[x] * m + ac);
+        }
+#pragma unroll
+        for (int x = 0; x < UNR; ++x) {
+          float part = vv[x].x * at(cc[x].x);
+          part = fmaf(vv[x].y, at(cc[x].y), part);
+          part = fmaf(vv[x].z, at(cc[x].z), part);
+          part = fmaf(vv[x].w, at(cc[x].w), part);
+          part = lane_has_data ? part : 0.f;
+#pragma unroll
+          for (int off = LPR >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
+          const bool use = row_ok && s[x] >= 0;
+          double q = use ? cost[x] + p.gamma * (double)part : INFINITY;
+          int aq = use ? a : 0x7fffffff;
+          wave_argmin_from<LPR>(q, aq);
+          const bool better = q < qb[x] || (q == qb[x] && aq < ab[x]);
+          qb[x] = better ? q : qb[x];
+          ab[x] = better ? aq : ab[x];
+        }
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int x = 0; x < UNR; ++x) {
+          if (s[x] < 0) continue;
+          const int av = ab[x] == 0x7fffffff ? 0 : ab[x];
+          if (improve)
+            commit_improve(p, s[x], qb[x], av, old[x], mode == kModeImproveCount, L);
+          else
+            commit_sweep(p, c, s[x], qb[x], av, old[x], L);
+        }
+      }
+    }
+  }
+};
+
 // ------------------------------------------------------------ general CSR engine
 
 struct CsrEngine {
+  static constexpr bool kBand = false;
+
   template <bool CE, bool IDENT>
   __device__ __forceinline__ static void batch(const KParams& p, const int32_t* ord, int64_t bk,
                                                const Ctx& c, int mode, Local& L) {
@@ -683,6 +920,9 @@ struct Driver {
   int64_t prev_count;     // states of the previous batch still to copy forward
   unsigned epoch;         // sweeps + improvement passes, selects accumulator slot
   int64_t gtid, gthreads;
+  // band-local engine: this workgroup's part of the previous batch, a run of
+  // list buffer band_prev_buf (-1: none yet)
+  int band_prev_buf, band_prev_lo, band_prev_hi;
 
   __device__ __forceinline__ explicit Driver(const KParams& kp) : p(kp) {
     g.ctl = p.ctl;
@@ -698,6 +938,8 @@ struct Driver {
     epoch = 0;
     gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     gthreads = (int64_t)gridDim.x * blockDim.x;
+    band_prev_buf = -1;
+    band_prev_lo = band_prev_hi = 0;
   }
 
   // Stamp of sweep t in first_mark (never 0, the cleared value).
@@ -741,6 +983,7 @@ struct Driver {
 
   template <class Eng, bool CE>
   __device__ __forceinline__ bool sweep(uint64_t t, int mode) {
+    if constexpr (Eng::kBand) return sweep_band<Eng, CE>(t, mode);
     const int64_t n = p.n, b = p.b, nb = (n + b - 1) / b;
     if (blockIdx.x == 0 && threadIdx.x == 0) reset_slot(p.ctl, (int)((epoch + 1) % 3));
     const int32_t* ord = p.order + (size_t)(t % 3) * (size_t)n;
@@ -770,8 +1013,62 @@ struct Driver {
     return true;
   }
 
+  // Band-local sweep: the workgroup computes the states of each batch that
+  // lie in its chunk, reading V from the batch's window in LDS.  It copies
+  // forward its own states of the previous batch (from the window, which
+  // holds them), except, in the first batch, those the batch rewrites.
+  template <class Eng, bool CE>
+  __device__ __forceinline__ bool sweep_band(uint64_t t, int mode) {
+    BandShared& sh = band_shared();
+    const BandGeom bg = band_geom(p);
+    const int nb = (int)((p.n + p.b - 1) / p.b);
+    const int buf = (int)(t & 1);
+    if (blockIdx.x == 0 && threadIdx.x == 0) reset_slot(p.ctl, (int)((epoch + 1) % 3));
+    band_sort(p, sh, bg, t, buf, nb);
+    for (int k = 0; k < nb; ++k) {
+      Ctx c{rd_buf(), wr_buf()};
+      for (int i = threadIdx.x; i < bg.wn; i += blockDim.x) sh.win[i] = c.rd[bg.wlo + i];
+      __syncthreads();
+      if (band_prev_buf >= 0) {
+        const uint16_t* prev = sh.lst[band_prev_buf];
+        for (int i = band_prev_lo + (int)threadIdx.x; i < band_prev_hi; i += blockDim.x) {
+          const int o = prev[i];
+          if (k == 0 && ((sh.first0[o >> 5] >> (o & 31)) & 1u)) continue;
+          c.wr[bg.c0 + o] = sh.win[bg.c0 + o - bg.wlo];
+        }
+      }
+      const int lo = sh.off[k], hi = sh.off[k + 1];
+      Eng::template batch_band<CE, false>(p, sh, sh.lst[buf] + lo, hi - lo, bg, c, mode, L);
+      band_prev_buf = buf;
+      band_prev_lo = lo;
+      band_prev_hi = hi;
+      if (k == nb - 1) flush_local(L, p.ctl, slot());
+      if (!grid_sync(g)) return false;
+      ++phase;
+    }
+    ++epoch;
+    return true;
+  }
+
+  template <class Eng, bool CE>
+  __device__ __forceinline__ bool improve_band(bool count) {
+    BandShared& sh = band_shared();
+    const BandGeom bg = band_geom(p);
+    if (blockIdx.x == 0 && threadIdx.x == 0) reset_slot(p.ctl, (int)((epoch + 1) % 3));
+    Ctx c{rd_buf(), wr_buf()};
+    for (int i = threadIdx.x; i < bg.wn; i += blockDim.x) sh.win[i] = c.rd[bg.wlo + i];
+    __syncthreads();
+    Eng::template batch_band<CE, true>(p, sh, nullptr, bg.dw, bg, c,
+                                       count ? kModeImproveCount : kModeImprove, L);
+    flush_local(L, p.ctl, slot());
+    if (!grid_sync(g)) return false;
+    ++epoch;
+    return true;
+  }
+
   template <class Eng, bool CE>
   __device__ __forceinline__ bool improve(bool count) {
+    if constexpr (Eng::kBand) return improve_band<Eng, CE>(count);
     if (blockIdx.x == 0 && threadIdx.x == 0) reset_slot(p.ctl, (int)((epoch + 1) % 3));
     Ctx c{rd_buf(), wr_buf()};
     Eng::template batch<CE, true>(p, nullptr, p.n, c, count ? kModeImproveCount : kModeImprove, L);
@@ -826,10 +1123,7 @@ struct Driver {
       }
     } else {
       if (cur != p.vbuf0)
-        for (int64_t i = gtid; i < prev_count; i += gthreads) {
-          const int32_t s = prev_order[i];
-          p.vbuf0[s] = cur[s];
-        }
+        for (int64_t s = gtid; s < p.n; s += gthreads) p.vbuf0[s] = cur[s];
       if (p.v64_out)
         for (int64_t s = gtid; s < p.n; s += gthreads) p.v64_out[s] = (double)cur[s];
     }
@@ -863,7 +1157,7 @@ solve_kernel(KParams p) {
     for (int64_t i = d.gtid; i < n * p.m; i += d.gthreads) p.ceff[i] = (double)p.c32[i];
   }
   long long since_recentre = 0;
-  d.fill_order(t, 0, min(p.b, n));
+  if constexpr (!Eng::kBand) d.fill_order(t, 0, min(p.b, n));
   if (blockIdx.x == 0 && threadIdx.x == 0) reset_slot(p.ctl, 0);
   if (!grid_sync(d.g)) return;
 
@@ -956,10 +1250,11 @@ __global__ void permutation_kernel(int64_t n, uint64_t seed, uint64_t t, int32_t
 
 // flags[0]: rows whose length differs from k; flags[1]: decreasing row_ptr
 // entries or entries outside [0, nnz]; flags[2]: row_ptr[0] != 0 or
-// row_ptr[rows] != nnz; flags[3]: columns outside [0, n).
+// row_ptr[rows] != nnz; flags[3]: columns outside [0, n); flags[4]: with k
+// rows of length k, max |s' - s| over the entries s' of the rows of state s.
 __global__ void csr_inspect_kernel(const int64_t* row_ptr, const int32_t* col, int64_t rows,
                                    int64_t n, int64_t nnz, int64_t k, unsigned long long* flags) {
-  unsigned long long not_k = 0, bad_ptr = 0, bad_col = 0;
+  unsigned long long not_k = 0, bad_ptr = 0, bad_col = 0, band = 0;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nth = (int64_t)gridDim.x * blockDim.x;
   for (int64_t r = tid; r < rows; r += nth) {
@@ -967,13 +1262,20 @@ __global__ void csr_inspect_kernel(const int64_t* row_ptr, const int32_t* col, i
     not_k += (b - a) != k;
     bad_ptr += (b < a) || a < 0 || b > nnz;
   }
+  const int64_t per_state = k > 0 ? k * (rows / n) : 0;  // entries of one state's rows
   for (int64_t e = tid; e < nnz; e += nth) {
     const int32_t c = col[e];
     bad_col += c < 0 || (int64_t)c >= n;
+    if (per_state > 0) {
+      const int64_t d = (int64_t)c - e / per_state;
+      const unsigned long long ad = (unsigned long long)(d < 0 ? -d : d);
+      band = ad > band ? ad : band;
+    }
   }
   if (not_k) atomicAdd(&flags[0], not_k);
   if (bad_ptr) atomicAdd(&flags[1], bad_ptr);
   if (bad_col) atomicAdd(&flags[3], bad_col);
+  if (band) atomicMax(&flags[4], band);
   if (tid == 0)
     if (row_ptr[0] != 0 || row_ptr[rows] != nnz) atomicAdd(&flags[2], 1ull);
 }
@@ -1088,12 +1390,32 @@ static SolveFn pick(const KParams& p, int units_per_wave_hint) {
   return solve_fn<CsrEngine>(p.task);
 }
 
-int launch_solve(KParams p, LaunchShape shape, void* stream, char* err, size_t errlen) {
-  const int waves_per_block = shape.threads / kWave;
-  // ELL: states per wavefront iteration from the batch size and a full grid
-  const int64_t waves_guess = (int64_t)shape.cus * shape.blocks_per_cu * waves_per_block;
-  const int64_t per_wave = waves_guess > 0 ? p.b / waves_guess : 1;
-  SolveFn f = pick(p, (int)(per_wave > 4 ? 4 : per_wave));
+// The band-local instantiation for ELL rows of LPR <= 16 lanes, or null.
+static SolveFn pick_band(const KParams& p, int units_per_wave_hint) {
+  int lpr = 1;
+  while (lpr * 4 < p.ell_k) lpr <<= 1;
+  const bool two = units_per_wave_hint >= 2;
+  switch (lpr) {
+    case 1: return two ? solve_fn<BandEngine<2, 1>>(p.task) : solve_fn<BandEngine<1, 1>>(p.task);
+    case 2: return two ? solve_fn<BandEngine<2, 2>>(p.task) : solve_fn<BandEngine<1, 2>>(p.task);
+    case 4: return two ? solve_fn<BandEngine<2, 4>>(p.task) : solve_fn<BandEngine<1, 4>>(p.task);
+    case 8: return two ? solve_fn<BandEngine<2, 8>>(p.task) : solve_fn<BandEngine<1, 8>>(p.task);
+    case 16: return two ? solve_fn<BandEngine<2, 16>>(p.task) : solve_fn<BandEngine<1, 16>>(p.task);
+    default: return nullptr;
+  }
+}
+
+// Whether the band-local engine's LDS holds a chunk, its window and the
+// batch offsets for a grid of `blocks` workgroups.
+static bool band_fits(const KParams& p, int blocks) {
+  if (p.storage != kEll || p.band < 0 || p.perm || blocks < 1) return false;
+  const int64_t D = (p.n + blocks - 1) / blocks;
+  const int64_t nb = (p.n + p.b - 1) / p.b;
+  return D <= kChunkCap && D + 2 * (int64_t)p.band <= kWinCap && nb <= kBatchCap;
+}
+
+static int grid_blocks(SolveFn f, const LaunchShape& shape, int* blocks, char* err,
+                       size_t errlen) {
   int occ = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
       &occ, reinterpret_cast<const void*>(f), shape.threads, 0);
@@ -1102,14 +1424,51 @@ int launch_solve(KParams p, LaunchShape shape, void* stream, char* err, size_t e
     return -1;
   }
   const int bpc = shape.blocks_per_cu < occ ? shape.blocks_per_cu : occ;
-  int blocks = shape.cus * bpc;
-  if (blocks > kMaxBlocks) blocks = kMaxBlocks;
+  *blocks = shape.cus * bpc;
+  if (*blocks > kMaxBlocks) *blocks = kMaxBlocks;
+  return 0;
+}
+
+// The instantiation a launch runs and its grid.
+static int choose(const KParams& p, const LaunchShape& shape, SolveFn* fn, int* blocks,
+                  int* engine, char* err, size_t errlen) {
+  const int waves_per_block = shape.threads / kWave;
+  // ELL: states per wavefront iteration from the batch size and a full grid
+  const int64_t waves_guess = (int64_t)shape.cus * shape.blocks_per_cu * waves_per_block;
+  const int64_t per_wave = waves_guess > 0 ? p.b / waves_guess : 1;
+  const int hint = (int)(per_wave > 4 ? 4 : per_wave);
+  if (p.storage == kEll && p.band >= 0 && !p.perm) {
+    SolveFn fb = pick_band(p, hint);
+    if (fb) {
+      if (grid_blocks(fb, shape, blocks, err, errlen) != 0) return -1;
+      if (band_fits(p, *blocks)) {
+        *fn = fb;
+        *engine = kEngineBand;
+        return 0;
+      }
+    }
+  }
+  *fn = pick(p, hint);
+  *engine = p.storage == kDense ? kEngineDense : p.storage == kEll ? kEngineEll : kEngineCsr;
+  return grid_blocks(*fn, shape, blocks, err, errlen);
+}
+
+int query_engine(const KParams& p, LaunchShape shape, int* engine, char* err, size_t errlen) {
+  SolveFn f = nullptr;
+  int blocks = 0;
+  return choose(p, shape, &f, &blocks, engine, err, errlen);
+}
+
+int launch_solve(KParams p, LaunchShape shape, void* stream, char* err, size_t errlen) {
+  SolveFn f = nullptr;
+  int blocks = 0, engine = 0;
+  if (choose(p, shape, &f, &blocks, &engine, err, errlen) != 0) return -1;
   // dense: split the columns of a state over several workgroups when the
   // batch has fewer states than there are workgroups
   p.splits = 1;
   if (p.storage == kDense && p.b < blocks) p.splits = (int)((blocks + p.b - 1) / p.b);
   void* args[] = {&p};
-  e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(f), dim3(blocks),
+  const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(f), dim3(blocks),
                                  dim3(shape.threads), args, 0,
                                  reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) {

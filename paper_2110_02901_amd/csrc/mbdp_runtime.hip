@@ -32,6 +32,7 @@ struct mbdp_mdp {
   const float* val;
   int64_t nnz;
   int32_t ell_k;
+  int32_t band;  // kEll: max |s' - s| over the entries of the rows of state s
   const float* c;
   int device;
   int cus;
@@ -126,6 +127,7 @@ KParams base_params(const mbdp_mdp* h, void* ws, float* V, int64_t b) {
   p.col = h->col;
   p.val = h->val;
   p.ell_k = h->ell_k;
+  p.band = (h->storage == kEll && h->tuning.band_window >= 0) ? h->band : -1;
   p.c32 = h->c;
   p.vbuf0 = V;
   p.vbuf1 = reinterpret_cast<float*>(base + w.vbuf1);
@@ -280,6 +282,7 @@ mbdp_status mdp_create_csr(int64_t n, int32_t m, const int64_t* row_ptr, const i
   if (flags[0] == 0 && k >= 4 && k <= 256 && k % 4 == 0) {
     h->storage = kEll;
     h->ell_k = (int32_t)k;
+    h->band = (int32_t)flags[4];
   }
   *out = h;
   return MBDP_OK;
@@ -295,6 +298,8 @@ mbdp_status mdp_set_tuning(mbdp_mdp_t h, const mbdp_tuning* t) {
   if (t->threads_per_block != 0 && t->threads_per_block != 256 && t->threads_per_block != 512 &&
       t->threads_per_block != 1024)
     return fail(MBDP_ERR_INVALID_ARG, "threads_per_block must be 0, 256, 512 or 1024");
+  if (t->band_window != 0 && t->band_window != -1)
+    return fail(MBDP_ERR_INVALID_ARG, "band_window must be 0 or -1");
   if (t->blocks_per_cu < 0 || t->blocks_per_cu > kMaxBlocksPerCu)
     return fail(MBDP_ERR_INVALID_ARG, "blocks_per_cu must be in [0, %d]", kMaxBlocksPerCu);
   h->tuning = *t;
@@ -304,6 +309,20 @@ mbdp_status mdp_set_tuning(mbdp_mdp_t h, const mbdp_tuning* t) {
 size_t mdp_workspace_bytes(mbdp_mdp_t h, int64_t b) {
   if (!h || b < 1 || b > h->n) return 0;
   return layout(h).total;
+}
+
+mbdp_status mdp_engine(mbdp_mdp_t h, int64_t b, const char** name) {
+  if (!h || !name) return fail(MBDP_ERR_INVALID_ARG, "handle or name is NULL");
+  *name = nullptr;
+  if (b < 1 || b > h->n) return fail(MBDP_ERR_INVALID_ARG, "b = %lld not in [1, n]", (long long)b);
+  KParams p = base_params(h, nullptr, nullptr, b);
+  p.task = kTaskVI;
+  int engine = 0;
+  char err[256] = {0};
+  if (query_engine(p, shape_of(h), &engine, err, sizeof err) != 0) return fail(MBDP_ERR_HIP, "%s", err);
+  static const char* const names[] = {"dense", "ell", "ell-band", "csr"};
+  *name = names[engine];
+  return MBDP_OK;
 }
 
 mbdp_status mdp_validate(mbdp_mdp_t h, double row_sum_tol, void* workspace, size_t ws_bytes,

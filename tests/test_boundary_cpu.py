@@ -95,6 +95,9 @@ def test_create_csr_argument_checks(lib):
 def test_calls_on_a_null_handle(lib):
     st = binding.Stats()
     assert lib.mdp_workspace_bytes(NULL, 1) == 0
+    name = ctypes.c_char_p()
+    assert lib.mdp_engine(NULL, 1, ctypes.byref(name)) == binding.MBDP_ERR_INVALID_ARG
+    assert name.value is None
     assert lib.mdp_destroy(NULL) == binding.MBDP_OK
     assert lib.mdp_set_tuning(NULL, None) == binding.MBDP_ERR_INVALID_ARG
     assert lib.mdp_validate(NULL, 1e-6, DUMMY, 1 << 20, NULL, None) == binding.MBDP_ERR_INVALID_ARG

@@ -89,7 +89,8 @@ def _sparse(name):
     rp, col, val, c = inputs.csr_mdp(wl["n"], wl["m"], wl["k"], wl["alpha"], wl["data_seed"],
                                      band=wl["band"])
     h, mdp = csr_case(rp, col, val, c, wl["gamma"])
-    say("%s generated and uploaded in %.1f s" % (name, time.time() - t0))
+    say("%s generated and uploaded in %.1f s; engine at b = 65536: %s"
+        % (name, time.time() - t0, mb.mdp_engine(h, 65536)))
     return wl, h, mdp
 
 

@@ -85,19 +85,34 @@ def test_vi_tight_tolerance_beyond_fp32(c1, b):
     assert np.array_equal(V.cpu().numpy(), V64.cpu().numpy().astype(np.float32))
 
 
+# "ell": the band-local engine; "ell-gather": the same MDP with V gathered
+# from memory (band window off).
+_ENGINE = {"dense": "dense", "ell": "ell-band", "ell-gather": "ell", "csr": "csr"}
+_WINDOW = {"ell-gather": -1}
+
+
 def _trajectory_case(storage):
     if storage == "dense":
         P, c = inputs.dense_mdp(1024, 16, 0.1, 2, dtype=np.float32)
-        return dense_case(P, c, 0.99)
-    if storage == "ell":
+        h, mdp = dense_case(P, c, 0.99)
+    elif storage.startswith("ell"):
         rp, col, val, c = inputs.csr_mdp(3000, 8, 32, 1.0, 3, band=64)
-        return csr_case(rp, col, val, c, 0.995)
-    rp, col, val, c = inputs.csr_ragged_mdp(500, 3, 1, 12, 1.0, 80)
-    return csr_case(rp, col, val, c, 0.95)
+        h, mdp = csr_case(rp, col, val, c, 0.995)
+    else:
+        rp, col, val, c = inputs.csr_ragged_mdp(500, 3, 1, 12, 1.0, 80)
+        h, mdp = csr_case(rp, col, val, c, 0.95)
+    _tune(h, storage)
+    assert mb.mdp_engine(h, 37) == _ENGINE[storage]
+    return h, mdp
+
+
+def _tune(h, storage, **kw):
+    mb.mdp_set_tuning(h, band_window=_WINDOW.get(storage, 0), **kw)
 
 
 @pytest.mark.parametrize("storage,b", [("dense", 1024), ("dense", 100), ("dense", 7),
                                        ("ell", 3000), ("ell", 1000), ("ell", 37),
+                                       ("ell-gather", 3000), ("ell-gather", 37),
                                        ("csr", 500), ("csr", 33)])
 @pytest.mark.parametrize("anchor", [False, True])
 def test_vi_trajectory_matches_oracle(storage, b, anchor):
@@ -108,7 +123,7 @@ def test_vi_trajectory_matches_oracle(storage, b, anchor):
     the size of one sweep's change."""
     h, mdp = _trajectory_case(storage)
     n, T = mdp.n, 6
-    mb.mdp_set_tuning(h, recentre_every=(1 if anchor else -1))
+    _tune(h, storage, recentre_every=(1 if anchor else -1))
     try:
         V0 = inputs.values(n, 31, 0.0, 3.0)
         ws = mb.workspace(h, b)
@@ -121,11 +136,11 @@ def test_vi_trajectory_matches_oracle(storage, b, anchor):
         assert np.max(np.abs(V64.cpu().numpy() - ref)) <= 1e-5 * scale
         assert np.max(np.abs(V.cpu().numpy() - ref)) <= 1e-5 * scale
     finally:
-        mb.mdp_set_tuning(h)
+        _tune(h, storage)
 
 
 @pytest.mark.parametrize("storage,b", [("dense", 1024), ("dense", 100), ("ell", 3000),
-                                       ("ell", 37), ("csr", 33)])
+                                       ("ell", 37), ("ell-gather", 37), ("csr", 33)])
 def test_vi_trajectory_with_recentring_every_sweep(storage, b):
     """Start next to J* and fold the iterate into the FP64 anchor after every
     sweep: the trajectory must still be the oracle's (which needs no
@@ -134,7 +149,7 @@ def test_vi_trajectory_with_recentring_every_sweep(storage, b):
     n, T = mdp.n, 5
     Vstar, _, _ = oracle.policy_iteration(mdp)
     V0 = (Vstar + inputs.values(n, 33, -1e-3, 1e-3, dtype=np.float64)).astype(np.float32)
-    mb.mdp_set_tuning(h, recentre_every=1, recentre_force=1)
+    _tune(h, storage, recentre_every=1, recentre_force=1)
     try:
         ws = mb.workspace(h, b)
         V = up(V0)
@@ -148,11 +163,12 @@ def test_vi_trajectory_with_recentring_every_sweep(storage, b):
         change = float(np.max(np.abs(ref - V0)))
         assert np.max(np.abs(V64.cpu().numpy() - ref)) <= 1e-2 * change
     finally:
-        mb.mdp_set_tuning(h)
+        _tune(h, storage)
 
 
 @pytest.mark.parametrize("storage,b", [("dense", 1024), ("dense", 100), ("ell", 3000),
-                                       ("ell", 37), ("csr", 33)])
+                                       ("ell", 37), ("ell-gather", 3000), ("ell-gather", 37),
+                                       ("csr", 33)])
 def test_mpi_trajectory_matches_oracle(storage, b):
     """Three outer iterations of MB-MPI (K = 2) in one launch against the
     oracle: values and policies after the last improvement."""
@@ -258,11 +274,13 @@ def test_mpi_dense_1024x16_reaches_eps(dense_1024):
     assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= out_tol(1e-6, Vstar)
 
 
+@pytest.mark.parametrize("window", [0, -1])
 @pytest.mark.parametrize("band", [64, None])
-def test_vi_and_mpi_sparse_reach_eps(band):
+def test_vi_and_mpi_sparse_reach_eps(band, window):
     n, m, k = 3000, 8, 32
     rp, col, val, c = inputs.csr_mdp(n, m, k, 1.0, 3, band=band)
     h, mdp = csr_case(rp, col, val, c, 0.995)
+    mb.mdp_set_tuning(h, band_window=window)
     Vstar, _, _ = oracle.policy_iteration(mdp)
     for b in (3000, 300):
         ws = mb.workspace(h, b)

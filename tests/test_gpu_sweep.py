@@ -133,11 +133,19 @@ def test_dense_inadmissible_actions():
 
 # ------------------------------------------------------------ sparse, constant row length
 
-@pytest.fixture(scope="module", params=["banded", "uniform"])
+# window 0: the band-local engine (every column of these small MDPs, even
+# the uniform one, falls in a window that fits in LDS); -1: V gathered
+# from memory by the plain ELL engine.
+@pytest.fixture(scope="module", params=[("banded", 0), ("uniform", 0), ("banded", -1),
+                                        ("uniform", -1)], ids=lambda p: "%s-w%d" % p)
 def ell_mid(request):
-    band = 64 if request.param == "banded" else None
+    kind, window = request.param
+    band = 64 if kind == "banded" else None
     rp, col, val, c = inputs.csr_mdp(3000, 8, 32, 1.0, 3, band=band)
-    return csr_case(rp, col, val, c, 0.995)
+    h, mdp = csr_case(rp, col, val, c, 0.995)
+    mb.mdp_set_tuning(h, band_window=window)
+    assert mb.mdp_engine(h, 100) == ("ell-band" if window == 0 else "ell")
+    return h, mdp
 
 
 @pytest.mark.parametrize("b", [1, 7, 100, 2999, 3000])
@@ -166,15 +174,52 @@ def test_ell_large_batches_several_states_per_wavefront(b):
     run_sweep(h, mdp, V0, b, 3, 1, policy=inputs.policy(n, m, 12))
 
 
+@pytest.mark.parametrize("window", [0, -1])
 @pytest.mark.parametrize("m,k", [(3, 4), (5, 12), (2, 64), (1, 256), (7, 8)])
-def test_ell_row_shapes(m, k):
+def test_ell_row_shapes(m, k, window):
     n = 700
     rp, col, val, c = inputs.csr_mdp(n, m, k, 1.0, 20 + k, band=None)
     h, mdp = csr_case(rp, col, val, c, 0.9)
+    mb.mdp_set_tuning(h, band_window=window)
+    # rows of more than 64 entries always gather from memory
+    assert mb.mdp_engine(h, 70) == ("ell-band" if window == 0 and k <= 64 else "ell")
     V0 = inputs.values(n, 11, 0.0, 9.0)
     for b in (1, 70, n):
         run_sweep(h, mdp, V0, b, 4, 0)
     run_sweep(h, mdp, V0, 70, 4, 1, policy=inputs.policy(n, m, 13))
+
+
+@pytest.mark.parametrize("n,b", [(40000, 40000), (40000, 999), (40000, 13), (200000, 7000)])
+def test_ell_band_engine_chunks_and_windows(n, b):
+    # narrow band (|s' - s| <= 300): chunks of n / 256 states per workgroup
+    # with 600 window entries beyond them; b = 13 gives more batches (3077)
+    # than a chunk has states.  Against the plain ELL engine and the oracle.
+    m, k = 4, 16
+    rp, col, val, c = inputs.csr_mdp(n, m, k, 1.0, 31, band=300)
+    h, mdp = csr_case(rp, col, val, c, 0.99)
+    assert mb.mdp_engine(h, b) == "ell-band"
+    V0 = inputs.values(n, 14, 5.0, 9.0)
+    Vb, _ = run_sweep(h, mdp, V0, b, 17, 2, check_arg=False)
+    run_sweep(h, mdp, V0, b, 17, 3, policy=inputs.policy(n, m, 15), check_arg=False)
+    mb.mdp_set_tuning(h, band_window=-1)
+    assert mb.mdp_engine(h, b) == "ell"
+    Ve, _ = run_sweep(h, mdp, V0, b, 17, 2, check_arg=False)
+    # same arithmetic in the same order per state: identical results
+    assert np.array_equal(Vb, Ve)
+
+
+def test_ell_band_engine_falls_back_when_the_window_does_not_fit():
+    n, m, k = 40000, 2, 8
+    rp, col, val, c = inputs.csr_mdp(n, m, k, 1.0, 32, band=9000)
+    h, mdp = csr_case(rp, col, val, c, 0.99)
+    assert mb.mdp_engine(h, 1000) == "ell"
+    # too many batches for the LDS offsets
+    rp, col, val, c = inputs.csr_mdp(n, m, k, 1.0, 33, band=100)
+    h2, mdp2 = csr_case(rp, col, val, c, 0.99)
+    assert mb.mdp_engine(h2, 1000) == "ell-band"
+    assert mb.mdp_engine(h2, 9) == "ell"
+    V0 = inputs.values(n, 16, 5.0, 9.0)
+    run_sweep(h2, mdp2, V0, 9, 18, 0, check_arg=False)
 
 
 # ------------------------------------------------------------ general CSR
