@@ -49,16 +49,106 @@ namespace mbdp {
 
 // ------------------------------------------------------------ accumulators
 
-struct Local {
-  double dv, err, wmax, wmin, resid;
+// Accumulators of the current epoch: max |dW|, max error against V_ref,
+// max |TW - W|, the range of W and the policy changes.  Two forms with one
+// interface.  RegAcc keeps them per thread in registers (committing lanes
+// only) and reduces them at the flush; LdsAcc keeps one copy per workgroup
+// in LDS, updated with LDS atomics, and holds no registers, for the dense
+// engine whose row tiles need every register (it commits few states).
+struct RegAcc {
+  double v[3];  // kAccDv, kAccErr, kAccResid slots below
+  double wmax, wmin;
   unsigned long long changes;
-  __device__ __forceinline__ void reset() {
-    dv = 0.0;
-    err = 0.0;
-    resid = 0.0;
+
+  __device__ __forceinline__ static int idx(int i) { return i == kAccDv ? 0 : (i == kAccErr ? 1 : 2); }
+  __device__ __forceinline__ void init() {
+    v[0] = v[1] = v[2] = 0.0;
     wmax = -INFINITY;
     wmin = INFINITY;
     changes = 0;
+  }
+  __device__ __forceinline__ void max_abs(int i, double x) { v[idx(i)] = fmax(v[idx(i)], x); }
+  __device__ __forceinline__ void range(double w) {
+    wmax = fmax(wmax, w);
+    wmin = fmin(wmin, w);
+  }
+  __device__ __forceinline__ void count_change() { changes += 1; }
+
+  // Merges the workgroup's values into epoch slot `slot` and clears them.
+  // Every thread of the workgroup must call it.
+  __device__ __forceinline__ void flush(Control* ctl, int slot) {
+    __shared__ double sh[16][5];
+    __shared__ unsigned long long shc[16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const double dv = wave_max_d(v[0]), err = wave_max_d(v[1]), res = wave_max_d(v[2]);
+    const double hi = wave_max_d(wmax), lo = wave_min_d(wmin);
+    unsigned long long ch = changes;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ch += __shfl_xor(ch, off);
+    if (lane == 0) {
+      sh[w][0] = dv;
+      sh[w][1] = err;
+      sh[w][2] = res;
+      sh[w][3] = hi;
+      sh[w][4] = lo;
+      shc[w] = ch;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a = sh[0][0], b = sh[0][1], c = sh[0][2], d = sh[0][3], e = sh[0][4];
+      unsigned long long f = shc[0];
+      for (int i = 1; i < nw; ++i) {
+        a = fmax(a, sh[i][0]);
+        b = fmax(b, sh[i][1]);
+        c = fmax(c, sh[i][2]);
+        d = fmax(d, sh[i][3]);
+        e = fmin(e, sh[i][4]);
+        f += shc[i];
+      }
+      unsigned long long* acc = ctl->acc[slot];
+      if (a > 0.0) atomicMax(&acc[kAccDv], (unsigned long long)__double_as_longlong(a));
+      if (b > 0.0) atomicMax(&acc[kAccErr], (unsigned long long)__double_as_longlong(b));
+      if (c > 0.0) atomicMax(&acc[kAccResid], (unsigned long long)__double_as_longlong(c));
+      if (d > -INFINITY) atomicMax(&acc[kAccWmax], okey(d));
+      if (e < INFINITY) atomicMin(&acc[kAccWmin], okey(e));
+      if (f) atomicAdd(&acc[kAccChanges], f);
+    }
+    __syncthreads();
+    init();
+  }
+};
+
+struct LdsAcc {
+  unsigned long long* a;  // [kNumAcc]: doubles >= 0 as bits, the W range as ordered keys
+
+  __device__ __forceinline__ void init() {
+    __shared__ unsigned long long acc[kNumAcc];
+    a = acc;
+    if (threadIdx.x == 0)  // visible after the next barrier, before any commit
+      for (int i = 0; i < kNumAcc; ++i) a[i] = (i == kAccWmin) ? ~0ull : 0ull;
+  }
+  __device__ __forceinline__ void max_abs(int i, double x) {  // NaN is ignored, as by fmax
+    if (x == x) atomicMax(&a[i], (unsigned long long)__double_as_longlong(x));
+  }
+  __device__ __forceinline__ void range(double w) {
+    atomicMax(&a[kAccWmax], okey(w));
+    atomicMin(&a[kAccWmin], okey(w));
+  }
+  __device__ __forceinline__ void count_change() { atomicAdd(&a[kAccChanges], 1ull); }
+
+  __device__ __forceinline__ void flush(Control* ctl, int slot) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long* acc = ctl->acc[slot];
+      if (a[kAccDv]) atomicMax(&acc[kAccDv], a[kAccDv]);
+      if (a[kAccErr]) atomicMax(&acc[kAccErr], a[kAccErr]);
+      if (a[kAccResid]) atomicMax(&acc[kAccResid], a[kAccResid]);
+      if (a[kAccWmax]) atomicMax(&acc[kAccWmax], a[kAccWmax]);
+      if (a[kAccWmin] != ~0ull) atomicMin(&acc[kAccWmin], a[kAccWmin]);
+      if (a[kAccChanges]) atomicAdd(&acc[kAccChanges], a[kAccChanges]);
+      for (int i = 0; i < kNumAcc; ++i) a[i] = (i == kAccWmin) ? ~0ull : 0ull;
+    }
+    __syncthreads();
   }
 };
 
@@ -68,48 +158,6 @@ __device__ __forceinline__ void reset_slot(Control* ctl, int slot) {
     if (i == kAccWmin) v = ~0ull;
     atomic_store_agent(&ctl->acc[slot][i], v);
   }
-}
-
-// Block-wide reduction of the per-thread accumulators into epoch slot `slot`.
-__device__ __forceinline__ void flush_local(Local& L, Control* ctl, int slot) {
-  __shared__ double sh[16][5];
-  __shared__ unsigned long long shc[16];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const double dv = wave_max_d(L.dv), err = wave_max_d(L.err), res = wave_max_d(L.resid);
-  const double wmax = wave_max_d(L.wmax), wmin = wave_min_d(L.wmin);
-  unsigned long long ch = L.changes;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) ch += __shfl_xor(ch, off);
-  if (lane == 0) {
-    sh[w][0] = dv;
-    sh[w][1] = err;
-    sh[w][2] = res;
-    sh[w][3] = wmax;
-    sh[w][4] = wmin;
-    shc[w] = ch;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = sh[0][0], b = sh[0][1], c = sh[0][2], d = sh[0][3], e = sh[0][4];
-    unsigned long long f = shc[0];
-    for (int i = 1; i < nw; ++i) {
-      a = fmax(a, sh[i][0]);
-      b = fmax(b, sh[i][1]);
-      c = fmax(c, sh[i][2]);
-      d = fmax(d, sh[i][3]);
-      e = fmin(e, sh[i][4]);
-      f += shc[i];
-    }
-    unsigned long long* acc = ctl->acc[slot];
-    if (a > 0.0) atomicMax(&acc[kAccDv], (unsigned long long)__double_as_longlong(a));
-    if (b > 0.0) atomicMax(&acc[kAccErr], (unsigned long long)__double_as_longlong(b));
-    if (c > 0.0) atomicMax(&acc[kAccResid], (unsigned long long)__double_as_longlong(c));
-    if (d > -INFINITY) atomicMax(&acc[kAccWmax], okey(d));
-    if (e < INFINITY) atomicMin(&acc[kAccWmin], okey(e));
-    if (f) atomicAdd(&acc[kAccChanges], f);
-  }
-  __syncthreads();
-  L.reset();
 }
 
 __device__ __forceinline__ double slot_double(Control* ctl, int slot, int i) {
@@ -137,38 +185,40 @@ __device__ __forceinline__ double cost_of(const KParams& p, int64_t row) {
 // New value of state s from the FP64 bracket minimum q with action a.  The
 // solvers iterate W = V - R for an FP64 anchor R (see Driver::recentre);
 // the error against V_ref is taken on W + R.
+template <class Acc>
 __device__ __forceinline__ void commit_sweep(const KParams& p, const Ctx& c, int32_t s, double q,
-                                             int a, float old, Local& L) {
+                                             int a, float old, Acc& L) {
   const float w = (float)q;
   c.wr[s] = w;
   if (p.argmin_out) p.argmin_out[s] = a;
-  L.dv = fmax(L.dv, fabs((double)w - (double)old));
-  if (p.vref) L.err = fmax(L.err, fabs(((double)w + (p.shift ? p.shift[s] : 0.0)) - p.vref[s]));
-  L.wmax = fmax(L.wmax, (double)w);
-  L.wmin = fmin(L.wmin, (double)w);
+  L.max_abs(kAccDv, fabs((double)w - (double)old));
+  if (p.vref) L.max_abs(kAccErr, fabs(((double)w + (p.shift ? p.shift[s] : 0.0)) - p.vref[s]));
+  L.range((double)w);
 }
 
 // Policy improvement of state s (Algorithm 1): V is not written.
+template <class Acc>
 __device__ __forceinline__ void commit_improve(const KParams& p, int32_t s, double q, int a,
-                                               float old, bool count, Local& L) {
-  if (count && p.policy[s] != a) L.changes += 1;
+                                               float old, bool count, Acc& L) {
+  if (count && p.policy[s] != a) L.count_change();
   p.policy[s] = a;
-  L.resid = fmax(L.resid, fabs(q - (double)old));
+  L.max_abs(kAccResid, fabs(q - (double)old));
 }
 
 enum Mode : int { kModeMin = 0, kModePolicy = 1, kModeImprove = 2, kModeImproveCount = 3 };
 
 // ------------------------------------------------------------ dense engine
 
-// acc[r] += sum_{j in [j0, j1), this thread's columns} rows[r][j] * V[j].
-// Row bases are uniform across the workgroup and column offsets are 32-bit,
-// so every load is a scalar base plus one vector offset.
+// acc[r] += sum_{j in [j0, j1), this thread's columns} rows[r][j] * V[j],
+// for thread tid of nthr threads sharing the rows.  Row bases are uniform
+// across the workgroup and column offsets are 32-bit, so every load is a
+// scalar base plus one vector offset.
 template <int R, int VEC, int U>
 __device__ __forceinline__ void dense_dot(const float* __restrict__ rows, uint32_t n, int nrows,
                                           const float* __restrict__ V, uint32_t j0, uint32_t j1,
-                                          float (&acc)[R]) {
-  const uint32_t step = blockDim.x * VEC;
-  for (uint32_t j = j0 + threadIdx.x * VEC; j < j1; j += step * U) {
+                                          uint32_t tid, uint32_t nthr, float (&acc)[R]) {
+  const uint32_t step = nthr * VEC;
+  for (uint32_t j = j0 + tid * VEC; j < j1; j += step * U) {
     if constexpr (VEC == 4) {
       f4 v[U];
       f4 x[U][R];
@@ -213,20 +263,23 @@ __device__ __forceinline__ void dense_dot(const float* __restrict__ rows, uint32
   }
 }
 
-// out[r] (LDS) = block-wide sum of acc[r], r < R.  Deterministic order.
+// out[g * R + r] (LDS) = sum of acc[r] over the wpg waves of group g (the
+// workgroup's waves split into consecutive groups of wpg), r < R, in a fixed
+// order.  Every thread of the workgroup must call it.
 template <int R>
-__device__ __forceinline__ void block_sum(float (&acc)[R], float* out) {
+__device__ __forceinline__ void group_sum(float (&acc)[R], float* out, int wpg) {
   __shared__ float red[16][16];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, groups = (blockDim.x >> 6) / wpg;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const float v = wave_sum(acc[r]);
     if (lane == 0) red[w][r] = v;
   }
   __syncthreads();
-  if (threadIdx.x < R) {
+  if ((int)threadIdx.x < R * groups) {
+    const int g = threadIdx.x / R, r = threadIdx.x % R;
     float s = 0.f;
-    for (int i = 0; i < nw; ++i) s += red[i][threadIdx.x];
+    for (int i = 0; i < wpg; ++i) s += red[g * wpg + i][r];
     out[threadIdx.x] = s;
   }
   __syncthreads();
@@ -256,6 +309,7 @@ constexpr int kMaxActions = 1024;
 template <int R, int VEC>
 struct DenseEngine {
   static constexpr bool kBand = false;
+  using Acc = LdsAcc;
 
   // Column range of split q of S, rounded to whole block-wide vector steps.
   __device__ __forceinline__ static void split_range(uint32_t n, int S, int q, uint32_t& j0,
@@ -272,12 +326,15 @@ struct DenseEngine {
     j1 = min(j0 + cs, n);
   }
 
-  // Processes this workgroup's units of one batch (ord == nullptr: the
-  // states are the positions themselves).
-  template <bool CE, bool IDENT>
+  // Processes this workgroup's units of one batch (IDENT: the states are
+  // the positions themselves).  Without column splits a workgroup with
+  // several states of the batch streams up to four of them at once, each
+  // with its own group of waves, so that the start-up latency of a state's
+  // row stream is paid once per group of states rather than per state.
+  template <bool CE, bool IDENT, class Acc>
   __device__ __forceinline__ static void batch(const KParams& p, const int32_t* ord, int64_t bk,
-                                               const Ctx& c, int mode, Local& L) {
-    __shared__ float s_sum[16];
+                                               const Ctx& c, int mode, Acc& L) {
+    __shared__ float s_sum[64];
     __shared__ double s_q[kMaxActions];
     __shared__ int s_last;
     const int64_t n = p.n;
@@ -286,30 +343,51 @@ struct DenseEngine {
     const int S = improve ? 1 : p.splits;
     const int64_t units = bk * S;
     const int mr = (mode == kModePolicy) ? 1 : m;  // rows of a state that are read
-    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
-      const int64_t i = u / S;
-      const int q = (int)(u % S);
+    // states streamed at once by one workgroup
+    const int nw = blockDim.x >> 6;
+    int G = 1;
+    if (S == 1) {
+      const int64_t per_wg = (units + gridDim.x - 1) / gridDim.x;
+      G = per_wg >= 4 ? 4 : (per_wg >= 2 ? 2 : 1);
+      while (G > 1 && (nw % G != 0 || G * m > kMaxActions)) G >>= 1;
+    }
+    const int wpg = nw / G;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
+    const int grp = wave / wpg;
+    const uint32_t gtid = threadIdx.x - (uint32_t)(grp * wpg * kWave);
+    const uint32_t gthr = (uint32_t)(wpg * kWave);
+    const bool lead_wave = (wave % wpg) == 0;
+    double* sq = s_q + grp * m;
+    for (int64_t ub = blockIdx.x; ub * G < units; ub += gridDim.x) {
+      const int64_t u = ub * G + grp;
+      const bool active = u < units;
+      const int64_t uc = active ? u : ub * G;
+      const int64_t i = uc / S;
+      const int q = (int)(uc % S);
       int32_t s;
       if constexpr (IDENT)
         s = (int32_t)i;
       else
         s = ord[i];
+      // the state is uniform over each wave: keep it (and the row bases) scalar
+      s = __builtin_amdgcn_readfirstlane(s);
       uint32_t j0, j1;
       split_range((uint32_t)n, S, q, j0, j1);
-      int apol = (mode == kModePolicy) ? p.policy[s] : 0;
+      int apol = (mode == kModePolicy) ? __builtin_amdgcn_readfirstlane(p.policy[s]) : 0;
       if (apol < 0 || apol >= m) {
-        if (threadIdx.x == 0) raise_abort(p.ctl, kDevBadPolicy);
+        if (active && gtid == 0) raise_abort(p.ctl, kDevBadPolicy);
         apol = 0;
       }
       // 1. partial dot products of the m (or 1) rows over [j0, j1)
       if (mode == kModePolicy) {
         float acc[1] = {0.f};
-        dense_dot<1, VEC, (VEC == 4 ? 8 : 16)>(p.P + ((size_t)s * m + apol) * (size_t)n,
-                                               (uint32_t)n, 1, c.rd, j0, j1, acc);
-        block_sum<1>(acc, s_sum);
-        if (threadIdx.x == 0) {
+        if (active)
+          dense_dot<1, VEC, (VEC == 4 ? 8 : 16)>(p.P + ((size_t)s * m + apol) * (size_t)n,
+                                                 (uint32_t)n, 1, c.rd, j0, j1, gtid, gthr, acc);
+        group_sum<1>(acc, s_sum, wpg);
+        if (active && gtid == 0) {
           if (S == 1)
-            s_q[0] = cost_of<CE>(p, (int64_t)s * m + apol) + p.gamma * (double)s_sum[0];
+            sq[0] = cost_of<CE>(p, (int64_t)s * m + apol) + p.gamma * (double)s_sum[grp];
           else
             p.partial[(size_t)(i * S + q)] = s_sum[0];
         }
@@ -319,19 +397,22 @@ struct DenseEngine {
           float acc[R];
 #pragma unroll
           for (int r = 0; r < R; ++r) acc[r] = 0.f;
-          dense_dot<R, VEC, (VEC == 4 ? (R >= 16 ? 1 : 16 / R) : 4)>(
-              p.P + ((size_t)s * m + a0) * (size_t)n, (uint32_t)n, nrows, c.rd, j0, j1, acc);
-          block_sum<R>(acc, s_sum);
-          if (threadIdx.x < nrows) {
-            const int a = a0 + threadIdx.x;
+          if (active)
+            dense_dot<R, VEC, (VEC == 4 ? (R >= 16 ? 1 : 16 / R) : 4)>(
+                p.P + ((size_t)s * m + a0) * (size_t)n, (uint32_t)n, nrows, c.rd, j0, j1, gtid,
+                gthr, acc);
+          group_sum<R>(acc, s_sum, wpg);
+          if (active && (int)gtid < nrows) {
+            const int a = a0 + gtid;
+            const float sum = s_sum[grp * R + gtid];
             if (S == 1)
-              s_q[a] = cost_of<CE>(p, (int64_t)s * m + a) + p.gamma * (double)s_sum[threadIdx.x];
+              sq[a] = cost_of<CE>(p, (int64_t)s * m + a) + p.gamma * (double)sum;
             else
-              p.partial[(size_t)(i * S + q) * m + a] = s_sum[threadIdx.x];
+              p.partial[(size_t)(i * S + q) * m + a] = sum;
           }
         }
       }
-      // 2. combine the splits: the last workgroup to arrive finishes the state
+      // 2. combine the splits (G == 1): the last workgroup to arrive finishes the state
       if (S > 1) {
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -354,16 +435,17 @@ struct DenseEngine {
         }
       }
       __syncthreads();
-      // 3. action minimum (lowest index on ties) and commit, in wave 0
-      if (threadIdx.x < kWave) {
+      // 3. action minimum (lowest index on ties) and commit, in the group's first wave
+      if (active && lead_wave) {
+        const int lane = threadIdx.x & 63;
         double qv = INFINITY;
         int av = 0x7fffffff;
         if (mode == kModePolicy) {
-          qv = s_q[0];
+          qv = sq[0];
           av = apol;
         } else {
-          for (int a = threadIdx.x; a < m; a += kWave) {
-            const double x = s_q[a];
+          for (int a = lane; a < m; a += kWave) {
+            const double x = sq[a];
             if (x < qv) {  // strictly smaller keeps the lowest index per lane
               qv = x;
               av = a;
@@ -372,7 +454,7 @@ struct DenseEngine {
           wave_argmin(qv, av);
           if (av == 0x7fffffff) av = 0;
         }
-        if (threadIdx.x == 0) {
+        if (lane == 0) {
           const float old = c.rd[s];
           if (improve)
             commit_improve(p, s, qv, av, old, mode == kModeImproveCount, L);
@@ -425,6 +507,7 @@ struct DenseEngine {
 template <int UNR, int LPR>
 struct EllEngine {
   static constexpr bool kBand = false;
+  using Acc = RegAcc;
 
 
   // One wavefront iteration serves UNR states (min modes) or UNR lane
@@ -436,9 +519,9 @@ struct EllEngine {
   // row read the row's first entries, rows past m read row m-1) and unused
   // results are discarded by selects, so the loads issue back to back
   // without branches.
-  template <bool CE, bool IDENT>
+  template <bool CE, bool IDENT, class Acc>
   __device__ __forceinline__ static void batch(const KParams& p, const int32_t* ord, int64_t bk,
-                                               const Ctx& c, int mode, Local& L) {
+                                               const Ctx& c, int mode, Acc& L) {
     const int m = p.m, k = p.ell_k;
     constexpr int lpr = LPR, rpp = kWave / LPR;
     const int lane = threadIdx.x & 63, g = lane / lpr, l = lane % lpr;
@@ -714,11 +797,11 @@ template <int UNR, int LPR>
 struct BandEngine : EllEngine<UNR, LPR> {
   static constexpr bool kBand = true;
 
-  template <bool CE, bool IDENT>
+  template <bool CE, bool IDENT, class Acc>
   __device__ __forceinline__ static void batch_band(const KParams& p, const BandShared& sh,
                                                     const uint16_t* lst, int cnt,
                                                     const BandGeom& bg, const Ctx& c, int mode,
-                                                    Local& L) {
+                                                    Acc& L) {
     const int m = p.m, k = p.ell_k;
     constexpr int rpp = kWave / LPR;
     const int lane = threadIdx.x & 63, g = lane / LPR, l = lane % LPR;
@@ -841,10 +924,11 @@ struct BandEngine : EllEngine<UNR, LPR> {
 
 struct CsrEngine {
   static constexpr bool kBand = false;
+  using Acc = RegAcc;
 
-  template <bool CE, bool IDENT>
+  template <bool CE, bool IDENT, class Acc>
   __device__ __forceinline__ static void batch(const KParams& p, const int32_t* ord, int64_t bk,
-                                               const Ctx& c, int mode, Local& L) {
+                                               const Ctx& c, int mode, Acc& L) {
     const int m = p.m;
     const int lane = threadIdx.x & 63;
     const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -909,10 +993,11 @@ struct CsrEngine {
 
 // ------------------------------------------------------------ the persistent kernel
 
+template <class Acc>
 struct Driver {
   const KParams& p;
   GridBarrier g;
-  Local L;
+  Acc L;
   float* buf0;
   float* buf1;
   int64_t phase;          // batches processed (parity selects the read buffer)
@@ -929,7 +1014,7 @@ struct Driver {
     g.gen = 0;
     g.nblocks = gridDim.x;
     g.timeout = p.timeout_ticks;
-    L.reset();
+    L.init();
     buf0 = p.vbuf0;
     buf1 = p.vbuf1;
     phase = 0;
@@ -1005,7 +1090,7 @@ struct Driver {
       Eng::template batch<CE, false>(p, ord + kb, bk, c, mode, L);
       prev_order = ord + kb;
       prev_count = bk;
-      if (k == nb - 1) flush_local(L, p.ctl, slot());
+      if (k == nb - 1) L.flush(p.ctl, slot());
       if (!grid_sync(g)) return false;
       ++phase;
     }
@@ -1042,7 +1127,7 @@ struct Driver {
       band_prev_buf = buf;
       band_prev_lo = lo;
       band_prev_hi = hi;
-      if (k == nb - 1) flush_local(L, p.ctl, slot());
+      if (k == nb - 1) L.flush(p.ctl, slot());
       if (!grid_sync(g)) return false;
       ++phase;
     }
@@ -1060,7 +1145,7 @@ struct Driver {
     __syncthreads();
     Eng::template batch_band<CE, true>(p, sh, nullptr, bg.dw, bg, c,
                                        count ? kModeImproveCount : kModeImprove, L);
-    flush_local(L, p.ctl, slot());
+    L.flush(p.ctl, slot());
     if (!grid_sync(g)) return false;
     ++epoch;
     return true;
@@ -1072,7 +1157,7 @@ struct Driver {
     if (blockIdx.x == 0 && threadIdx.x == 0) reset_slot(p.ctl, (int)((epoch + 1) % 3));
     Ctx c{rd_buf(), wr_buf()};
     Eng::template batch<CE, true>(p, nullptr, p.n, c, count ? kModeImproveCount : kModeImprove, L);
-    flush_local(L, p.ctl, slot());
+    L.flush(p.ctl, slot());
     if (!grid_sync(g)) return false;
     ++epoch;
     return true;
@@ -1146,7 +1231,7 @@ struct Driver {
 template <class Eng, int TASK>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)))
 solve_kernel(KParams p) {
-  Driver d(p);
+  Driver<typename Eng::Acc> d(p);
   const int64_t n = p.n;
   uint64_t t = p.first_sweep;
   // prologue: second buffer, row sums and shifted costs, first order
