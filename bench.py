@@ -65,29 +65,29 @@ def committed_traffic(workload, sweeps_per_launch):
     return sweeps_per_launch * per_sweep + prologue
 
 
-def cpu_baseline(P, c, gamma, b, seed, budget_s=20.0):
-    """The FP64 oracle's sweeps on the same dense MDP, timed on the host."""
+def cpu_baseline(mdp, wl_name, b, seed, budget_s=20.0):
+    """The FP64 oracle's sweeps on the same MDP, timed on the host: whole
+    sweeps from V = 0 until the budget is spent (at least one)."""
     import oracle
     try:
         from threadpoolctl import threadpool_info
         cores = max((t.get("num_threads", 1) for t in threadpool_info()), default=1)
     except Exception:
         cores = 1
-    mdp = oracle.DenseMDP(P, c, gamma)
-    V = np.zeros(P.shape[0])
+    n, m = mdp.n, mdp.m
+    V = np.zeros(n)
     sweeps = 0
     t0 = time.perf_counter()
     while True:
-        V, _, _ = oracle.mb_sweep(mdp, V, b, oracle.sweep_permutation(P.shape[0], seed, sweeps))
+        V, _, _ = oracle.mb_sweep(mdp, V, b, oracle.sweep_permutation(n, seed, sweeps))
         sweeps += 1
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    n, m = c.shape
     return {"value": sweeps * n * m / dt, "unit": "backups/s", "cores": int(cores),
             "kind": "oracle",
-            "sample": "%d FP64 sweeps of B_b (b=%d) on the full n=%d, m=%d dense MDP from V=0, "
-                      "%.1f s" % (sweeps, b, n, m, dt)}
+            "sample": "%d FP64 sweeps of B_b (b=%d) on the full %s MDP (n=%d, m=%d) from V=0, "
+                      "%.1f s" % (sweeps, b, wl_name, n, m, dt)}
 
 
 def main():
@@ -106,8 +106,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--profile-sweeps", type=int, default=0,
-                    help="only run one vi_solve of exactly this many sweeps at the first "
-                         "batch size (per-sweep counter measurement)")
+                    help="only run two vi_solve launches of exactly S and 3 S sweeps at the "
+                         "first batch size (per-sweep counters: the difference of the two)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the mini-batch sweep is built and timed on a "
@@ -164,18 +164,20 @@ def main():
 
     if args.profile_sweeps:
         b = batch_sizes[0]
-        V = torch.zeros(n, dtype=torch.float32, device=dev)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        st = mb.vi_solve(h, V, b, seed, ws, tol_dv=-1.0, max_sweeps=args.profile_sweeps)
-        e1.record(stream)
-        e1.synchronize()
-        ms = e0.elapsed_time(e1)
-        print(json.dumps({"profile_sweeps": st["sweeps"], "b": b, "ms": ms,
-                          "algorithmic_bytes": st["sweeps"] * n * m * bytes_per_backup,
-                          "algorithmic_bytes_per_sweep": n * m * bytes_per_backup,
-                          "library_hash": library_hash()}))
+        out = {"b": b, "engine": mb.mdp_engine(h, b), "launches": [],
+               "algorithmic_bytes_per_sweep": n * m * bytes_per_backup,
+               "library_hash": library_hash()}
+        for sweeps in (args.profile_sweeps, 3 * args.profile_sweeps):
+            V = torch.zeros(n, dtype=torch.float32, device=dev)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            st = mb.vi_solve(h, V, b, seed, ws, tol_dv=-1.0, max_sweeps=sweeps)
+            e1.record(stream)
+            e1.synchronize()
+            out["launches"].append({"sweeps": st["sweeps"], "recentrings": st["recentrings"],
+                                    "ms": e0.elapsed_time(e1)})
+        print(json.dumps(out))
         return
 
     # Reference V* for the time-to-eps rule (not timed): MPI at b = n until
@@ -248,6 +250,7 @@ def main():
     value = backups / wall
     kernel_gbps = backups * bytes_per_backup / total_s / 1e9
     traffic = committed_traffic(wl_name, total_sweeps / args.steps)
+    engine = mb.mdp_engine(h, best_b)
 
     line = {
         "metric": METRIC,
@@ -283,14 +286,17 @@ def main():
             "unit": "GB/s",
             "frac": kernel_gbps / HBM_PEAK_GBPS,
             "traffic": traffic,
-            "kernel": ("solve_kernel<DenseEngine<16,4>, VI>" if dense
-                       else "solve_kernel<EllEngine<%d>, VI>" % (2 if best_b >= 8192 else 1)),
+            "kernel": "solve_kernel, %s engine, VI (one launch per solve)" % engine,
             "algorithmic_bytes_per_backup": bytes_per_backup,
         },
     }
-    if not args.no_cpu_baseline and dense:
+    if not args.no_cpu_baseline:
         log("timing the CPU oracle (~%.0f s)" % args.cpu_baseline_seconds)
-        line["cpu_baseline"] = cpu_baseline(P, c, gamma, best_b, seed, args.cpu_baseline_seconds)
+        import oracle
+        mdp = (oracle.DenseMDP(P, c, gamma) if dense
+               else oracle.CsrMDP(rp, col, val, c, gamma))
+        line["cpu_baseline"] = cpu_baseline(mdp, wl_name, best_b, seed,
+                                            args.cpu_baseline_seconds)
     print(json.dumps(line), flush=True)
 
 

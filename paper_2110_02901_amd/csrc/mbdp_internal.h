@@ -68,6 +68,7 @@ struct KParams {
   const float* c32;        // plain costs [n*m]
   double* ceff;            // shifted costs [n*m] (solvers), workspace
   double* shift;           // FP64 anchor R[n] with V = W + R (solvers), workspace
+  double* tgt;             // V_ref - R [n] (solvers; zeros without a reference), workspace
   double* v64_out;         // optional FP64 copy of the final V
   // vectors
   float* vbuf0;            // caller's V
@@ -106,7 +107,7 @@ struct KParams {
 
 // Workspace layout, shared by the size query and the launches.
 struct WsLayout {
-  size_t ctl, unit_count, partial, order, first_mark, vbuf1, ceff, shift, total;
+  size_t ctl, unit_count, partial, order, first_mark, vbuf1, ceff, shift, tgt, total;
   size_t zero_bytes;  // prefix cleared before every launch (control + counters)
 };
 
@@ -129,6 +130,7 @@ inline WsLayout ws_layout(int32_t storage, int64_t n, int32_t m, int64_t max_uni
   w.vbuf1 = off;      off = align_up(off + (size_t)n * sizeof(float), 256);
   w.ceff = off;       off = align_up(off + (size_t)n * (size_t)m * sizeof(double), 256);
   w.shift = off;      off = align_up(off + (size_t)n * sizeof(double), 256);
+  w.tgt = off;        off = align_up(off + (size_t)n * sizeof(double), 256);
   w.total = off;
   return w;
 }

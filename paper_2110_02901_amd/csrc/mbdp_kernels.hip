@@ -182,30 +182,53 @@ __device__ __forceinline__ double cost_of(const KParams& p, int64_t row) {
     return (double)p.c32[row];
 }
 
+// What a state's commit needs besides its new value is loaded with the
+// state's row data, so that the commit waits for no further memory round
+// trip: in the sweeps of a solve, aux = V_ref(s) - R(s) (kept in the
+// workspace array tgt), the target of the error check W + R - V_ref =
+// W - aux; in improvement passes, the old policy entry.  The loads are
+// unconditional, so no wait is placed before the row loads.
+template <bool CE, bool IDENT>
+__device__ __forceinline__ double commit_aux(const KParams& p, int32_t s) {
+  if constexpr (IDENT)
+    return (double)p.policy[s];
+  else if constexpr (CE)
+    return p.tgt[s];
+  else
+    return 0.0;
+}
+
+// Marks aux as used by every lane here.  Only one lane per state commits;
+// without a use on the other lanes' path the load of aux would still count
+// as pending at the loop's back edge, and the compiler would wait for all
+// memory operations (the commit's stores included) before the next
+// iteration's loads.  aux was loaded with the row data, so it has arrived.
+__device__ __forceinline__ void consume(double aux) { __asm__ volatile("" ::"v"(aux)); }
+
 // New value of state s from the FP64 bracket minimum q with action a.  The
-// solvers iterate W = V - R for an FP64 anchor R (see Driver::recentre);
-// the error against V_ref is taken on W + R.
+// solvers iterate W = V - R for an FP64 anchor R (see Driver::recentre).
 template <class Acc>
 __device__ __forceinline__ void commit_sweep(const KParams& p, const Ctx& c, int32_t s, double q,
-                                             int a, float old, Acc& L) {
+                                             int a, float old, double aux, Acc& L) {
   const float w = (float)q;
   c.wr[s] = w;
   if (p.argmin_out) p.argmin_out[s] = a;
   L.max_abs(kAccDv, fabs((double)w - (double)old));
-  if (p.vref) L.max_abs(kAccErr, fabs(((double)w + (p.shift ? p.shift[s] : 0.0)) - p.vref[s]));
+  if (p.vref) L.max_abs(kAccErr, fabs((double)w - aux));
   L.range((double)w);
 }
 
 // Policy improvement of state s (Algorithm 1): V is not written.
 template <class Acc>
 __device__ __forceinline__ void commit_improve(const KParams& p, int32_t s, double q, int a,
-                                               float old, bool count, Acc& L) {
-  if (count && p.policy[s] != a) L.count_change();
+                                               float old, bool count, double aux, Acc& L) {
+  if (count && (int)aux != a) L.count_change();
   p.policy[s] = a;
   L.max_abs(kAccResid, fabs(q - (double)old));
 }
 
 enum Mode : int { kModeMin = 0, kModePolicy = 1, kModeImprove = 2, kModeImproveCount = 3 };
+
 
 // ------------------------------------------------------------ dense engine
 
@@ -412,6 +435,9 @@ struct DenseEngine {
           }
         }
       }
+      // the commit's inputs (issued before the reductions that precede the commit)
+      const float old = c.rd[s];
+      const double aux = commit_aux<CE, IDENT>(p, s);
       // 2. combine the splits (G == 1): the last workgroup to arrive finishes the state
       if (S > 1) {
         __syncthreads();
@@ -435,6 +461,7 @@ struct DenseEngine {
         }
       }
       __syncthreads();
+      consume(aux);
       // 3. action minimum (lowest index on ties) and commit, in the group's first wave
       if (active && lead_wave) {
         const int lane = threadIdx.x & 63;
@@ -454,12 +481,12 @@ struct DenseEngine {
           wave_argmin(qv, av);
           if (av == 0x7fffffff) av = 0;
         }
+        consume(aux);
         if (lane == 0) {
-          const float old = c.rd[s];
           if (improve)
-            commit_improve(p, s, qv, av, old, mode == kModeImproveCount, L);
+            commit_improve(p, s, qv, av, old, mode == kModeImproveCount, aux, L);
           else
-            commit_sweep(p, c, s, qv, av, old, L);
+            commit_sweep(p, c, s, qv, av, old, aux, L);
         }
       }
       __syncthreads();
@@ -553,11 +580,13 @@ struct EllEngine {
     for (int64_t u = gw; u < units; u += nw) {
       int32_t s[UNR], sc[UNR];
       float old[UNR];
+      double aux[UNR];
 #pragma unroll
       for (int x = 0; x < UNR; ++x) {
         s[x] = s_next[x];
         sc[x] = s[x] >= 0 ? s[x] : 0;
         old[x] = rd[sc[x]];
+        aux[x] = commit_aux<CE, IDENT>(p, sc[x]);
       }
       if (pol) {
         int a[UNR];
@@ -592,8 +621,9 @@ struct EllEngine {
           part = lane_has_data ? part : 0.f;
           #pragma unroll
           for (int off = LPR >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
+          consume(aux[x]);
           if (l == 0 && s[x] >= 0)
-            commit_sweep(p, c, s[x], cost[x] + p.gamma * (double)part, a[x], old[x], L);
+            commit_sweep(p, c, s[x], cost[x] + p.gamma * (double)part, a[x], old[x], aux[x], L);
         }
         continue;
       }
@@ -636,7 +666,9 @@ struct EllEngine {
           #pragma unroll
           for (int off = LPR >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
           const bool use = row_ok && s[x] >= 0;
-          double q = use ? cost[x] + p.gamma * (double)part : INFINITY;
+          // computed on every lane, then selected: keeps the cost load unconditional
+          const double qa = cost[x] + p.gamma * (double)part;
+          double q = use ? qa : INFINITY;
           int aq = use ? a : 0x7fffffff;
           wave_argmin_from<LPR>(q, aq);
           const bool better = q < qb[x] || (q == qb[x] && aq < ab[x]);
@@ -644,15 +676,17 @@ struct EllEngine {
           ab[x] = better ? aq : ab[x];
         }
       }
+#pragma unroll
+      for (int x = 0; x < UNR; ++x) consume(aux[x]);
       if (lane == 0) {
 #pragma unroll
         for (int x = 0; x < UNR; ++x) {
           if (s[x] < 0) continue;
           const int av = ab[x] == 0x7fffffff ? 0 : ab[x];
           if (improve)
-            commit_improve(p, s[x], qb[x], av, old[x], mode == kModeImproveCount, L);
+            commit_improve(p, s[x], qb[x], av, old[x], mode == kModeImproveCount, aux[x], L);
           else
-            commit_sweep(p, c, s[x], qb[x], av, old[x], L);
+            commit_sweep(p, c, s[x], qb[x], av, old[x], aux[x], L);
         }
       }
     }
@@ -820,6 +854,7 @@ struct BandEngine : EllEngine<UNR, LPR> {
     for (int u = wv; u < units; u += nwv) {
       int32_t s[UNR], sc[UNR];
       float old[UNR];
+      double aux[UNR];
 #pragma unroll
       for (int x = 0; x < UNR; ++x) {
         const int pos = pol ? u * per_unit + x * rpp + g : u * per_unit + x;
@@ -833,6 +868,7 @@ struct BandEngine : EllEngine<UNR, LPR> {
         sc[x] = (int32_t)bg.c0 + o;
         s[x] = valid ? sc[x] : -1;
         old[x] = at(sc[x]);
+        aux[x] = commit_aux<CE, IDENT>(p, sc[x]);
       }
       if (pol) {
         int a[UNR];
@@ -861,8 +897,9 @@ struct BandEngine : EllEngine<UNR, LPR> {
           part = lane_has_data ? part : 0.f;
 #pragma unroll
           for (int off = LPR >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
+          consume(aux[x]);
           if (l == 0 && s[x] >= 0)
-            commit_sweep(p, c, s[x], cost[x] + p.gamma * (double)part, a[x], old[x], L);
+            commit_sweep(p, c, s[x], cost[x] + p.gamma * (double)part, a[x], old[x], aux[x], L);
         }
         continue;
       }
@@ -897,7 +934,9 @@ struct BandEngine : EllEngine<UNR, LPR> {
 #pragma unroll
           for (int off = LPR >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
           const bool use = row_ok && s[x] >= 0;
-          double q = use ? cost[x] + p.gamma * (double)part : INFINITY;
+          // computed on every lane, then selected: keeps the cost load unconditional
+          const double qa = cost[x] + p.gamma * (double)part;
+          double q = use ? qa : INFINITY;
           int aq = use ? a : 0x7fffffff;
           wave_argmin_from<LPR>(q, aq);
           const bool better = q < qb[x] || (q == qb[x] && aq < ab[x]);
@@ -905,15 +944,17 @@ struct BandEngine : EllEngine<UNR, LPR> {
           ab[x] = better ? aq : ab[x];
         }
       }
+#pragma unroll
+      for (int x = 0; x < UNR; ++x) consume(aux[x]);
       if (lane == 0) {
 #pragma unroll
         for (int x = 0; x < UNR; ++x) {
           if (s[x] < 0) continue;
           const int av = ab[x] == 0x7fffffff ? 0 : ab[x];
           if (improve)
-            commit_improve(p, s[x], qb[x], av, old[x], mode == kModeImproveCount, L);
+            commit_improve(p, s[x], qb[x], av, old[x], mode == kModeImproveCount, aux[x], L);
           else
-            commit_sweep(p, c, s[x], qb[x], av, old[x], L);
+            commit_sweep(p, c, s[x], qb[x], av, old[x], aux[x], L);
         }
       }
     }
@@ -940,6 +981,8 @@ struct CsrEngine {
         s = (int32_t)u;
       else
         s = ord[u];
+      const float old = c.rd[s];
+      const double aux = commit_aux<CE, IDENT>(p, s);
       double qb = INFINITY;
       int ab = 0x7fffffff;
       int a_lo = mode == kModePolicy ? p.policy[s] : 0;
@@ -962,12 +1005,12 @@ struct CsrEngine {
         }
       }
       if (ab == 0x7fffffff) ab = a_lo;
+      consume(aux);
       if (lane == 0) {
-        const float old = c.rd[s];
         if (improve)
-          commit_improve(p, s, qb, ab, old, mode == kModeImproveCount, L);
+          commit_improve(p, s, qb, ab, old, mode == kModeImproveCount, aux, L);
         else
-          commit_sweep(p, c, s, qb, ab, old, L);
+          commit_sweep(p, c, s, qb, ab, old, aux, L);
       }
     }
   }
@@ -1174,7 +1217,9 @@ struct Driver {
   __device__ __forceinline__ bool recentre(long long& count) {
     const float* cur = rd_buf();
     for (int64_t s = gtid; s < p.n; s += gthreads) {
-      p.shift[s] += (double)cur[s];
+      const double r = p.shift[s] + (double)cur[s];
+      p.shift[s] = r;
+      if (p.vref) p.tgt[s] = p.vref[s] - r;
       buf0[s] = 0.f;
       buf1[s] = 0.f;
     }
@@ -1239,6 +1284,7 @@ solve_kernel(KParams p) {
   if (TASK != kTaskSweep) {
     if (p.shift)
       for (int64_t s = d.gtid; s < n; s += d.gthreads) p.shift[s] = 0.0;
+    for (int64_t s = d.gtid; s < n; s += d.gthreads) p.tgt[s] = p.vref ? p.vref[s] : 0.0;
     for (int64_t i = d.gtid; i < n * p.m; i += d.gthreads) p.ceff[i] = (double)p.c32[i];
   }
   long long since_recentre = 0;

@@ -433,6 +433,7 @@ mbdp_status vi_solve(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy_ou
   p.recentre_every = recentre_interval(h);
   p.recentre_force = h->tuning.recentre_force != 0;
   p.ceff = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.ceff);
+  p.tgt = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.tgt);
   if (p.recentre_every > 0)
     p.shift = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.shift);
   st = launch(h, p, workspace, stream);
@@ -479,6 +480,7 @@ mbdp_status mpi_solve(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy,
   p.recentre_every = recentre_interval(h);
   p.recentre_force = h->tuning.recentre_force != 0;
   p.ceff = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.ceff);
+  p.tgt = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.tgt);
   if (p.recentre_every > 0)
     p.shift = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.shift);
   st = launch(h, p, workspace, stream);
