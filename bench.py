@@ -43,10 +43,10 @@ def library_hash():
     return h.hexdigest()[:16]
 
 
-def committed_traffic(workload, sweeps_per_launch):
+def committed_traffic(workload, b, sweeps_per_launch):
     """HBM bytes per launch from the committed rocprofv3 counter summary
     (sweeps x bytes per sweep + the one-off prologue), if the counters were
-    taken with the current kernel sources; else None."""
+    taken with the current kernel sources at this batch size; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % workload)
     if not os.path.exists(path):
         return None
@@ -55,7 +55,7 @@ def committed_traffic(workload, sweeps_per_launch):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("library_hash") != library_hash():
+    if vals.get("library_hash") != library_hash() or vals.get("b") != str(b):
         return None
     try:
         per_sweep = float(vals["hbm_bytes_per_sweep"])
@@ -249,7 +249,7 @@ def main():
     backups = total_sweeps * n * m
     value = backups / wall
     kernel_gbps = backups * bytes_per_backup / total_s / 1e9
-    traffic = committed_traffic(wl_name, total_sweeps / args.steps)
+    traffic = committed_traffic(wl_name, best_b, total_sweeps / args.steps)
     engine = mb.mdp_engine(h, best_b)
 
     line = {
