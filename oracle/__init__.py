@@ -20,6 +20,9 @@ Lygeros; arXiv 2110.02901):
                      policy iteration (Algorithm 1), exact policy evaluation
                      (eq. (4)), Howard policy iteration and brute-force
                      enumeration of J* (eq. (2)).
+* ``quantize``    -- BF16 / FP8 E4M3 storage of transition rows with one
+                     scale per row renormalising it to sum 1 (the reduced-
+                     precision variant; the paper fixes no precision).
 
 Notation: the paper's batch size ``m`` is called ``b`` here, because ``m`` is
 the number of actions; the paper's cost-to-go ``J`` is ``V`` and its discount
