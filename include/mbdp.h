@@ -95,6 +95,13 @@ typedef struct {
                                   when it fits, -1 never does (V is gathered from memory) */
 } mbdp_tuning;
 
+/* Storage types of the transition probabilities. */
+typedef enum {
+  MBDP_F32 = 0,      /* IEEE binary32 */
+  MBDP_BF16 = 1,     /* bfloat16 codes (uint16) with one FP32 scale per row */
+  MBDP_FP8_E4M3 = 2  /* OCP FP8 E4M3FN codes (uint8) with one FP32 scale per row */
+} mbdp_dtype;
+
 /* Dense MDP (P as in Sec. II-A, stored [n][m][n]).  Records the pointers;
  * does no device work.  P and c are device arrays. */
 mbdp_status mdp_create_dense(int64_t n, int32_t m, const float* P, const float* c,
@@ -111,6 +118,37 @@ mbdp_status mdp_create_csr(int64_t n, int32_t m, const int64_t* row_ptr, const i
 
 /* Releases the handle (not the borrowed arrays).  NULL is a no-op. */
 mbdp_status mdp_destroy(mbdp_mdp_t h);
+
+/* Reduced-precision storage (the paper fixes no precision; this variant
+ * trades accuracy for bytes per backup).  Row r of `rows` FP32 rows of
+ * `row_len` entries (device, row-major, `src`) is stored as codes q_r in
+ * `dst` (device; uint16 per entry for MBDP_BF16, uint8 for MBDP_FP8_E4M3)
+ * and one FP32 scale in `row_scale[r]` (device) such that the stored row
+ * P'(r, j) = row_scale[r] * decode(q_rj) sums to 1 (row_scale = 1 / sum_j
+ * decode(q_rj), summed in FP64; 0 for a row that encodes to zeros).
+ * Encoding rounds to nearest, ties to even.  FP8 rows are first multiplied
+ * by the power of two 2^(7 - E), E the binary exponent of the row's largest
+ * magnitude (clamped to [-100, 127]), an exact scaling that places the
+ * largest entry in [128, 256); values beyond 448 saturate.  The MDP that the
+ * BF16 / FP8 handles below solve is P', not the FP32 input: its solution
+ * differs from the FP32 one by up to ~ gamma / (1 - gamma) times the
+ * relative storage error (2^-9 BF16, 2^-4 FP8).  Asynchronous on `stream`. */
+mbdp_status mdp_quantize_rows(const float* src, int64_t rows, int64_t row_len, int32_t dtype,
+                              void* dst, float* row_scale, hipStream_t stream);
+
+/* Dense MDP with P stored as BF16 / FP8 codes [n][m][n] and row scales
+ * [n*m] (as written by mdp_quantize_rows).  n must be a multiple of 8
+ * (BF16) or 16 (FP8), else MBDP_ERR_UNSUPPORTED.  Borrowed pointers. */
+mbdp_status mdp_create_dense_q(int64_t n, int32_t m, const void* P, int32_t dtype,
+                               const float* row_scale, const float* c, double gamma,
+                               mbdp_mdp_t* out);
+
+/* Sparse MDP with BF16 / FP8 values and row scales [n*m].  Needs a constant
+ * row length k with k % 4 == 0 and 4 <= k <= 64 (else
+ * MBDP_ERR_UNSUPPORTED); otherwise as mdp_create_csr. */
+mbdp_status mdp_create_csr_q(int64_t n, int32_t m, const int64_t* row_ptr, const int32_t* col,
+                             const void* val, int32_t dtype, const float* row_scale, int64_t nnz,
+                             const float* c, double gamma, hipStream_t stream, mbdp_mdp_t* out);
 
 /* Replaces the handle's tuning knobs. */
 mbdp_status mdp_set_tuning(mbdp_mdp_t h, const mbdp_tuning* t);

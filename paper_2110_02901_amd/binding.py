@@ -22,6 +22,12 @@ MBDP_ERR_NOT_CONVERGED = 5
 MBDP_ERR_VALIDATION = 6
 MBDP_ERR_DEVICE = 7
 
+# storage types of transition probabilities (mbdp_dtype)
+MBDP_F32 = 0
+MBDP_BF16 = 1
+MBDP_FP8_E4M3 = 2
+DTYPES = {"bf16": MBDP_BF16, "fp8": MBDP_FP8_E4M3}
+
 STATUS_NAMES = {
     0: "MBDP_OK", 1: "MBDP_ERR_INVALID_ARG", 2: "MBDP_ERR_UNSUPPORTED",
     3: "MBDP_ERR_WORKSPACE", 4: "MBDP_ERR_HIP", 5: "MBDP_ERR_NOT_CONVERGED",
@@ -30,7 +36,8 @@ STATUS_NAMES = {
 
 # Every symbol include/mbdp.h declares.
 EXPORTS = [
-    "mdp_create_dense", "mdp_create_csr", "mdp_destroy", "mdp_set_tuning",
+    "mdp_create_dense", "mdp_create_csr", "mdp_create_dense_q", "mdp_create_csr_q",
+    "mdp_quantize_rows", "mdp_destroy", "mdp_set_tuning",
     "mdp_workspace_bytes", "mdp_engine", "mdp_validate", "mbdp_permutation", "mb_sweep",
     "mbdp_sync_status", "vi_solve", "mpi_solve", "mbdp_last_error",
 ]
@@ -82,6 +89,10 @@ _SIGS = {
     "mdp_create_dense": (_I32, [_I64, _I32, _P, _P, _D, ctypes.POINTER(_P)]),
     "mdp_create_csr": (_I32, [_I64, _I32, _P, _P, _P, _I64, _P, _D, _P, ctypes.POINTER(_P)]),
     "mdp_destroy": (_I32, [_P]),
+    "mdp_create_dense_q": (_I32, [_I64, _I32, _P, _I32, _P, _P, _D, ctypes.POINTER(_P)]),
+    "mdp_create_csr_q": (_I32, [_I64, _I32, _P, _P, _P, _I32, _P, _I64, _P, _D, _P,
+                                ctypes.POINTER(_P)]),
+    "mdp_quantize_rows": (_I32, [_P, _I64, _I64, _I32, _P, _P, _P]),
     "mdp_set_tuning": (_I32, [_P, ctypes.POINTER(Tuning)]),
     "mdp_workspace_bytes": (ctypes.c_size_t, [_P, _I64]),
     "mdp_engine": (_I32, [_P, _I64, ctypes.POINTER(ctypes.c_char_p)]),
@@ -192,6 +203,58 @@ def mdp_create_csr(row_ptr, col, val, c, gamma, stream=None):
     _check(lib().mdp_create_csr(n, m, _ptr(row_ptr), _ptr(col), _ptr(val), col.numel(),
                                 _ptr(c), float(gamma), _stream(stream), ctypes.byref(h)))
     return Handle(h, n, m, (row_ptr, col, val, c))
+
+
+def _code_dtype(dtype):
+    import torch
+    return torch.int16 if dtype == "bf16" else torch.uint8
+
+
+def mdp_quantize_rows(src, dtype, stream=None):
+    """src: FP32 [rows, row_len] on the GPU.  Returns (codes, row_scale):
+    int16 (BF16 bit patterns) or uint8 (FP8 E4M3) codes of the same shape and
+    FP32 scales [rows], written by the library's quantiser."""
+    import torch
+    rows, row_len = src.shape
+    _require(src, torch.float32, None, "src")
+    codes = torch.empty((rows, row_len), dtype=_code_dtype(dtype), device=src.device)
+    scale = torch.empty(rows, dtype=torch.float32, device=src.device)
+    _check(lib().mdp_quantize_rows(_ptr(src), rows, row_len, DTYPES[dtype], _ptr(codes),
+                                   _ptr(scale), _stream(stream)))
+    return codes, scale
+
+
+def mdp_create_dense_q(Pq, dtype, row_scale, c, gamma):
+    """Dense MDP from BF16 / FP8 codes [n*m*n] and row scales [n*m]."""
+    import torch
+    n, m = c.shape
+    _require(Pq, _code_dtype(dtype), None, "P")
+    if Pq.numel() != n * m * n:
+        raise ValueError("P must have %d elements, got %d" % (n * m * n, Pq.numel()))
+    _require(row_scale, torch.float32, n * m, "row_scale")
+    _require(c, torch.float32, n * m, "c")
+    h = ctypes.c_void_p()
+    _check(lib().mdp_create_dense_q(n, m, _ptr(Pq), DTYPES[dtype], _ptr(row_scale), _ptr(c),
+                                    float(gamma), ctypes.byref(h)))
+    return Handle(h, n, m, (Pq, row_scale, c))
+
+
+def mdp_create_csr_q(row_ptr, col, valq, dtype, row_scale, c, gamma, stream=None):
+    """Sparse MDP with BF16 / FP8 values (constant row length k <= 64)."""
+    import torch
+    n, m = c.shape
+    _require(row_ptr, torch.int64, n * m + 1, "row_ptr")
+    _require(col, torch.int32, None, "col")
+    _require(valq, _code_dtype(dtype), None, "val")
+    if valq.numel() != col.numel():
+        raise ValueError("val must have %d elements, got %d" % (col.numel(), valq.numel()))
+    _require(row_scale, torch.float32, n * m, "row_scale")
+    _require(c, torch.float32, n * m, "c")
+    h = ctypes.c_void_p()
+    _check(lib().mdp_create_csr_q(n, m, _ptr(row_ptr), _ptr(col), _ptr(valq), DTYPES[dtype],
+                                  _ptr(row_scale), col.numel(), _ptr(c), float(gamma),
+                                  _stream(stream), ctypes.byref(h)))
+    return Handle(h, n, m, (row_ptr, col, valq, row_scale, c))
 
 
 def mdp_destroy(h):

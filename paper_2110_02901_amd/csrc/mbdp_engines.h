@@ -232,6 +232,84 @@ __device__ __forceinline__ void commit_improve(const KParams& p, int32_t s, doub
 enum Mode : int { kModeMin = 0, kModePolicy = 1, kModeImprove = 2, kModeImproveCount = 3 };
 
 
+// ------------------------------------------------------------ storage of P
+//
+// Transition values are FP32, or BF16 / FP8 E4M3 (OCP E4M3FN) with one FP32
+// scale per row: P(r, j) = scale_r * decode(q_rj).  Decoding is exact (BF16 is
+// the upper half of an FP32; FP8 goes through the hardware converter), the
+// dot products accumulate the decoded values in FP32 and the row scale is
+// applied once per row, in FP64 with the cost.
+
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float bf16_lo(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(unsigned w) { return __uint_as_float(w & 0xFFFF0000u); }
+
+__device__ __forceinline__ f4 fp8x4(unsigned w) {
+  const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, false);  // bytes 0, 1
+  const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, true);   // bytes 2, 3
+  return f4{lo[0], lo[1], hi[0], hi[1]};
+}
+
+struct ValF32 {
+  static constexpr int kType = kF32;
+  static constexpr int kBytes = 4;
+  // ELL entries e .. e+3 (e a multiple of 4)
+  __device__ __forceinline__ static f4 ell4(const KParams& p, size_t e) {
+    return __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e));
+  }
+  __device__ __forceinline__ static float scale(const KParams&, int64_t) { return 1.f; }
+  __device__ __forceinline__ static float dense_at(const KParams& p, size_t i) {
+    return __builtin_nontemporal_load(p.P + i);
+  }
+};
+
+struct ValBF16 {
+  static constexpr int kType = kBF16;
+  static constexpr int kBytes = 2;
+  __device__ __forceinline__ static f4 ell4(const KParams& p, size_t e) {
+    const u2 w = __builtin_nontemporal_load(
+        reinterpret_cast<const u2*>(static_cast<const uint16_t*>(p.pq) + e));
+    return f4{bf16_lo(w.x), bf16_hi(w.x), bf16_lo(w.y), bf16_hi(w.y)};
+  }
+  __device__ __forceinline__ static float scale(const KParams& p, int64_t row) {
+    return p.rscale[row];
+  }
+  __device__ __forceinline__ static float dense_at(const KParams& p, size_t i) {
+    return __uint_as_float((unsigned)static_cast<const uint16_t*>(p.pq)[i] << 16);
+  }
+  // word w (values 2w, 2w+1) of a 16-byte load of 8 values, times V
+  __device__ __forceinline__ static void fma_word(unsigned x, int w, const f4* v, float& acc) {
+    const f4& vv = v[w >> 1];
+    acc = fmaf(bf16_lo(x), (w & 1) ? vv.z : vv.x, acc);
+    acc = fmaf(bf16_hi(x), (w & 1) ? vv.w : vv.y, acc);
+  }
+};
+
+struct ValFP8 {
+  static constexpr int kType = kFP8;
+  static constexpr int kBytes = 1;
+  __device__ __forceinline__ static f4 ell4(const KParams& p, size_t e) {
+    return fp8x4(__builtin_nontemporal_load(
+        reinterpret_cast<const unsigned*>(static_cast<const uint8_t*>(p.pq) + e)));
+  }
+  __device__ __forceinline__ static float scale(const KParams& p, int64_t row) {
+    return p.rscale[row];
+  }
+  __device__ __forceinline__ static float dense_at(const KParams& p, size_t i) {
+    return fp8x4((unsigned)static_cast<const uint8_t*>(p.pq)[i]).x;
+  }
+  // word w (values 4w .. 4w+3) of a 16-byte load of 16 values, times V
+  __device__ __forceinline__ static void fma_word(unsigned x, int w, const f4* v, float& acc) {
+    const f4 d = fp8x4(x);
+    acc = fmaf(d.x, v[w].x, acc);
+    acc = fmaf(d.y, v[w].y, acc);
+    acc = fmaf(d.z, v[w].z, acc);
+    acc = fmaf(d.w, v[w].w, acc);
+  }
+};
+
 // ------------------------------------------------------------ dense engine
 
 // acc[r] += sum_{j in [j0, j1), this thread's columns} rows[r][j] * V[j],
@@ -288,6 +366,44 @@ __device__ __forceinline__ void dense_dot(const float* __restrict__ rows, uint32
   }
 }
 
+// The same for BF16 / FP8 rows: each 16-byte load holds EPL = 16 / kBytes
+// consecutive values of a row, decoded and multiplied by EPL values of V.
+// rows is the byte address of the first row; n % EPL == 0.
+template <int R, class T, int U>
+__device__ __forceinline__ void dense_dot_q(const uint8_t* __restrict__ rows, uint32_t n,
+                                            int nrows, const float* __restrict__ V, uint32_t j0,
+                                            uint32_t j1, uint32_t tid, uint32_t nthr,
+                                            float (&acc)[R]) {
+  constexpr int EPL = 16 / T::kBytes;
+  const uint32_t step = nthr * EPL;
+  const size_t rbytes = (size_t)n * T::kBytes;
+  for (uint32_t j = j0 + tid * EPL; j < j1; j += step * U) {
+    f4 v[U][EPL / 4];
+    u4 x[U][R];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t jj = j + u * step;
+      const bool ok = jj < j1;
+#pragma unroll
+      for (int q = 0; q < EPL / 4; ++q)
+        v[u][q] = ok ? *reinterpret_cast<const f4*>(V + jj + 4 * q) : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        x[u][r] = (ok && r < nrows)
+                      ? __builtin_nontemporal_load(reinterpret_cast<const u4*>(
+                            rows + (size_t)r * rbytes + (size_t)jj * T::kBytes))
+                      : u4{0u, 0u, 0u, 0u};
+    }
+    // word by word across the rows, so each decoded word dies at once
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int w = 0; w < 4; ++w)
+#pragma unroll
+        for (int r = 0; r < R; ++r) T::fma_word(x[u][r][w], w, v[u], acc[r]);
+  }
+}
+
 // out[g * R + r] (LDS) = sum of acc[r] over the wpg waves of group g (the
 // workgroup's waves split into consecutive groups of wpg), r < R, in a fixed
 // order.  Every thread of the workgroup must call it.
@@ -331,10 +447,31 @@ __device__ __forceinline__ void block_sum_d(double (&acc)[R], double* out) {
 
 constexpr int kMaxActions = 1024;
 
-template <int R, int VEC>
+template <int R, int VEC, class T = ValF32>
 struct DenseEngine {
   static constexpr bool kBand = false;
   using Acc = LdsAcc;
+  // 16-byte row loads in flight per thread and step: 16 for FP32 and BF16;
+  // 8 for FP8, whose tiles also hold 16 values of V per load
+  static constexpr int kLoads = T::kType == kFP8 ? 8 : 16;
+  // (at most 4 steps at once: each step also holds VEC values of V)
+  static constexpr int kRowUnroll = VEC == 1 ? 4 : (R >= kLoads ? 1 : (kLoads / R < 4 ? kLoads / R : 4));
+  // one row per state in policy sweeps: a BF16 / FP8 row of n values is
+  // n * 2 or n bytes, at most a few loads per thread
+  static constexpr int kPolicyUnroll = VEC == 1 ? 16 : (T::kType == kF32 ? 8 : 2);
+
+  // Partial dot products of the rows row0 .. row0+nrows-1 (VEC: FP32 values
+  // per load, or the values of one 16-byte load for BF16 / FP8).
+  template <int RR, int U>
+  __device__ __forceinline__ static void dot(const KParams& p, size_t row0, uint32_t n,
+                                             int nrows, const float* V, uint32_t j0, uint32_t j1,
+                                             uint32_t tid, uint32_t nthr, float (&acc)[RR]) {
+    if constexpr (T::kType == kF32)
+      dense_dot<RR, VEC, U>(p.P + row0 * n, n, nrows, V, j0, j1, tid, nthr, acc);
+    else
+      dense_dot_q<RR, T, U>(static_cast<const uint8_t*>(p.pq) + row0 * n * T::kBytes, n, nrows,
+                            V, j0, j1, tid, nthr, acc);
+  }
 
   // Column range of split q of S, rounded to whole block-wide vector steps.
   __device__ __forceinline__ static void split_range(uint32_t n, int S, int q, uint32_t& j0,
@@ -407,12 +544,13 @@ struct DenseEngine {
       if (mode == kModePolicy) {
         float acc[1] = {0.f};
         if (active)
-          dense_dot<1, VEC, (VEC == 4 ? 8 : 16)>(p.P + ((size_t)s * m + apol) * (size_t)n,
-                                                 (uint32_t)n, 1, c.rd, j0, j1, gtid, gthr, acc);
+          dot<1, kPolicyUnroll>(p, (size_t)s * m + apol, (uint32_t)n, 1, c.rd, j0, j1, gtid, gthr,
+                                acc);
         group_sum<1>(acc, s_sum, wpg);
         if (active && gtid == 0) {
+          const int64_t row = (int64_t)s * m + apol;
           if (S == 1)
-            sq[0] = cost_of<CE>(p, (int64_t)s * m + apol) + p.gamma * (double)s_sum[grp];
+            sq[0] = cost_of<CE>(p, row) + p.gamma * ((double)s_sum[grp] * (double)T::scale(p, row));
           else
             p.partial[(size_t)(i * S + q)] = s_sum[0];
         }
@@ -423,15 +561,15 @@ struct DenseEngine {
 #pragma unroll
           for (int r = 0; r < R; ++r) acc[r] = 0.f;
           if (active)
-            dense_dot<R, VEC, (VEC == 4 ? (R >= 16 ? 1 : 16 / R) : 4)>(
-                p.P + ((size_t)s * m + a0) * (size_t)n, (uint32_t)n, nrows, c.rd, j0, j1, gtid,
-                gthr, acc);
+            dot<R, kRowUnroll>(p, (size_t)s * m + a0, (uint32_t)n, nrows, c.rd, j0, j1, gtid,
+                               gthr, acc);
           group_sum<R>(acc, s_sum, wpg);
           if (active && (int)gtid < nrows) {
             const int a = a0 + gtid;
+            const int64_t row = (int64_t)s * m + a;
             const float sum = s_sum[grp * R + gtid];
             if (S == 1)
-              sq[a] = cost_of<CE>(p, (int64_t)s * m + a) + p.gamma * (double)sum;
+              sq[a] = cost_of<CE>(p, row) + p.gamma * ((double)sum * (double)T::scale(p, row));
             else
               p.partial[(size_t)(i * S + q) * m + a] = sum;
           }
@@ -458,8 +596,8 @@ struct DenseEngine {
         for (int a = threadIdx.x; a < mr; a += blockDim.x) {
           double sum = 0.0;
           for (int qq = 0; qq < S; ++qq) sum += (double)p.partial[(size_t)(i * S + qq) * mr + a];
-          const int act = (mode == kModePolicy) ? apol : a;
-          s_q[a] = cost_of<CE>(p, (int64_t)s * m + act) + p.gamma * sum;
+          const int64_t row = (int64_t)s * m + ((mode == kModePolicy) ? apol : a);
+          s_q[a] = cost_of<CE>(p, row) + p.gamma * (sum * (double)T::scale(p, row));
         }
       }
       __syncthreads();
@@ -504,7 +642,7 @@ struct DenseEngine {
       const double rs = p.shift[s];
       for (int a0 = 0; a0 < m; a0 += R) {
         const int nrows = min(R, m - a0);
-        const float* rows = p.P + ((size_t)s * m + a0) * (size_t)n;
+        const size_t base = ((size_t)s * m + a0) * (size_t)n;
         double acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = 0.0;
@@ -513,12 +651,13 @@ struct DenseEngine {
 #pragma unroll
           for (int r = 0; r < R; ++r)
             if (r < nrows)
-              acc[r] = fma((double)__builtin_nontemporal_load(rows + (size_t)r * n + j), rj, acc[r]);
+              acc[r] = fma((double)T::dense_at(p, base + (size_t)r * n + j), rj, acc[r]);
         }
         block_sum_d<R>(acc, s_sumd);
         if (threadIdx.x < nrows) {
           const int64_t row = (int64_t)s * m + a0 + threadIdx.x;
-          p.ceff[row] = (double)p.c32[row] - rs + p.gamma * s_sumd[threadIdx.x];
+          p.ceff[row] = (double)p.c32[row] - rs +
+                        p.gamma * (s_sumd[threadIdx.x] * (double)T::scale(p, row));
         }
       }
     }
@@ -533,7 +672,7 @@ struct DenseEngine {
 // time; in the policy mode each lane group serves its own state.  LPR is a
 // template parameter so that the lane reductions unroll with constant
 // shuffle offsets.
-template <int UNR, int LPR>
+template <int UNR, int LPR, class T = ValF32>
 struct EllEngine {
   static constexpr bool kBand = false;
   using Acc = RegAcc;
@@ -595,6 +734,7 @@ struct EllEngine {
         i4 cc[UNR];
         f4 vv[UNR];
         double cost[UNR];
+        float scl[UNR];
 #pragma unroll
         for (int x = 0; x < UNR; ++x) {
           int av = p.policy[sc[x]];
@@ -605,8 +745,9 @@ struct EllEngine {
           a[x] = av;
           const size_t e = ((size_t)sc[x] * m + av) * (size_t)k + (size_t)lcol;
           cc[x] = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e));
-          vv[x] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e));
+          vv[x] = T::ell4(p, e);
           cost[x] = cost_of<CE>(p, (int64_t)sc[x] * m + av);
+          scl[x] = T::scale(p, (int64_t)sc[x] * m + av);
         }
 #pragma unroll
         for (int x = 0; x < UNR; ++x) s_next[x] = state_at(u + nw, x);
@@ -625,7 +766,8 @@ struct EllEngine {
           for (int off = LPR >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
           consume(aux[x]);
           if (l == 0 && s[x] >= 0)
-            commit_sweep(p, c, s[x], cost[x] + p.gamma * (double)part, a[x], old[x], aux[x], L);
+            commit_sweep(p, c, s[x], cost[x] + p.gamma * ((double)part * (double)scl[x]), a[x],
+                         old[x], aux[x], L);
         }
         continue;
       }
@@ -643,12 +785,14 @@ struct EllEngine {
         i4 cc[UNR];
         f4 vv[UNR];
         double cost[UNR];
+        float scl[UNR];
 #pragma unroll
         for (int x = 0; x < UNR; ++x) {
           const size_t e = ((size_t)sc[x] * m + ac) * (size_t)k + (size_t)lcol;
           cc[x] = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e));
-          vv[x] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e));
+          vv[x] = T::ell4(p, e);
           cost[x] = cost_of<CE>(p, (int64_t)sc[x] * m + ac);
+          scl[x] = T::scale(p, (int64_t)sc[x] * m + ac);
         }
         if (a0 == 0) {
 #pragma unroll
@@ -669,7 +813,7 @@ struct EllEngine {
           for (int off = LPR >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
           const bool use = row_ok && s[x] >= 0;
           // computed on every lane, then selected: keeps the cost load unconditional
-          const double qa = cost[x] + p.gamma * (double)part;
+          const double qa = cost[x] + p.gamma * ((double)part * (double)scl[x]);
           double q = use ? qa : INFINITY;
           int aq = use ? a : 0x7fffffff;
           wave_argmin_from<LPR>(q, aq);
@@ -710,7 +854,7 @@ struct EllEngine {
         if (a < m && lane_has_data) {
           const size_t e = ((size_t)s * m + a) * (size_t)k + (size_t)l * 4;
           const i4 cc = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e));
-          const f4 vv = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e));
+          const f4 vv = T::ell4(p, e);
           part = (double)vv.x * p.shift[cc.x] + (double)vv.y * p.shift[cc.y] +
                  (double)vv.z * p.shift[cc.z] + (double)vv.w * p.shift[cc.w];
         }
@@ -718,7 +862,7 @@ struct EllEngine {
           for (int off = LPR >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
         if (l == 0 && a < m) {
           const int64_t row = s * m + a;
-          p.ceff[row] = (double)p.c32[row] - rs + p.gamma * part;
+          p.ceff[row] = (double)p.c32[row] - rs + p.gamma * (part * (double)T::scale(p, row));
         }
       }
     }
@@ -829,8 +973,8 @@ __device__ __forceinline__ void band_sort(const KParams& p, BandShared& sh, cons
 // The ELL loop of EllEngine with state ids from the workgroup's list and V
 // read from the window in LDS.  Row streams, costs and policies still come
 // from memory; the recentring pass (shift_costs) is EllEngine's.
-template <int UNR, int LPR>
-struct BandEngine : EllEngine<UNR, LPR> {
+template <int UNR, int LPR, class T = ValF32>
+struct BandEngine : EllEngine<UNR, LPR, T> {
   static constexpr bool kBand = true;
 
   template <bool CE, bool IDENT, class Acc>
@@ -877,6 +1021,7 @@ struct BandEngine : EllEngine<UNR, LPR> {
         i4 cc[UNR];
         f4 vv[UNR];
         double cost[UNR];
+        float scl[UNR];
 #pragma unroll
         for (int x = 0; x < UNR; ++x) {
           int av = p.policy[sc[x]];
@@ -887,8 +1032,9 @@ struct BandEngine : EllEngine<UNR, LPR> {
           a[x] = av;
           const size_t e = ((size_t)sc[x] * m + av) * (size_t)k + (size_t)lcol;
           cc[x] = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e));
-          vv[x] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e));
+          vv[x] = T::ell4(p, e);
           cost[x] = cost_of<CE>(p, (int64_t)sc[x] * m + av);
+          scl[x] = T::scale(p, (int64_t)sc[x] * m + av);
         }
 #pragma unroll
         for (int x = 0; x < UNR; ++x) {
@@ -901,7 +1047,8 @@ struct BandEngine : EllEngine<UNR, LPR> {
           for (int off = LPR >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
           consume(aux[x]);
           if (l == 0 && s[x] >= 0)
-            commit_sweep(p, c, s[x], cost[x] + p.gamma * (double)part, a[x], old[x], aux[x], L);
+            commit_sweep(p, c, s[x], cost[x] + p.gamma * ((double)part * (double)scl[x]), a[x],
+                         old[x], aux[x], L);
         }
         continue;
       }
@@ -919,12 +1066,14 @@ struct BandEngine : EllEngine<UNR, LPR> {
         i4 cc[UNR];
         f4 vv[UNR];
         double cost[UNR];
+        float scl[UNR];
 #pragma unroll
         for (int x = 0; x < UNR; ++x) {
           const size_t e = ((size_t)sc[x] * m + ac) * (size_t)k + (size_t)lcol;
           cc[x] = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p.col + e));
-          vv[x] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p.val + e));
+          vv[x] = T::ell4(p, e);
           cost[x] = cost_of<CE>(p, (int64_t)sc[x] * m + ac);
+          scl[x] = T::scale(p, (int64_t)sc[x] * m + ac);
         }
 #pragma unroll
         for (int x = 0; x < UNR; ++x) {
@@ -937,7 +1086,7 @@ struct BandEngine : EllEngine<UNR, LPR> {
           for (int off = LPR >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
           const bool use = row_ok && s[x] >= 0;
           // computed on every lane, then selected: keeps the cost load unconditional
-          const double qa = cost[x] + p.gamma * (double)part;
+          const double qa = cost[x] + p.gamma * ((double)part * (double)scl[x]);
           double q = use ? qa : INFINITY;
           int aq = use ? a : 0x7fffffff;
           wave_argmin_from<LPR>(q, aq);
@@ -1366,8 +1515,7 @@ solve_kernel(KParams p) {
   d.finish(sweeps, outer, changes_last, recentrings, last_dv, last_err, converged);
 }
 
-// The kernel a launch runs, and its instantiation for an engine and task.
-typedef void (*SolveFn)(KParams);
+// The instantiation of the solve kernel for an engine and task.
 
 template <class Eng>
 inline SolveFn solve_fn(int task) {

@@ -8,6 +8,8 @@
 namespace mbdp {
 
 enum Storage : int32_t { kDense = 0, kEll = 1, kCsr = 2 };
+// Storage of transition probabilities (values of mbdp_dtype in include/mbdp.h).
+enum ValueType : int32_t { kF32 = 0, kBF16 = 1, kFP8 = 2 };
 enum Task : int32_t { kTaskSweep = 0, kTaskVI = 1, kTaskMPI = 2 };
 
 // Device-side error codes recorded in Control::error.
@@ -59,12 +61,16 @@ struct KParams {
   int32_t m;
   int64_t n;
   double gamma;
-  const float* P;          // dense [n][m][n]
+  const float* P;          // dense [n][m][n] (FP32 storage)
   const int64_t* row_ptr;  // CSR
   const int32_t* col;
   const float* val;
   int32_t ell_k;           // constant row length (kEll), else 0
   int32_t band;            // kEll: max |s' - s| over the entries of state s's rows; -1 unknown or off
+  int32_t vdtype;          // storage of the transition values: kF32, kBF16, kFP8
+  int32_t pad3;
+  const void* pq;          // BF16 / FP8 values: dense [n][m][n], or ELL [nnz]
+  const float* rscale;     // BF16 / FP8: per-row scale, P(r, j) = rscale[r] * decode(q_rj)
   const float* c32;        // plain costs [n*m]
   double* ceff;            // shifted costs [n*m] (solvers), workspace
   double* shift;           // FP64 anchor R[n] with V = W + R (solvers), workspace
@@ -157,5 +163,14 @@ int launch_permutation(int64_t n, uint64_t seed, uint64_t t, int32_t* out, void*
 int launch_csr_inspect(const int64_t* row_ptr, const int32_t* col, int64_t rows, int64_t n,
                        int64_t nnz, int64_t k, unsigned long long* flags, void* stream);
 int launch_validate(const KParams& p, double tol, unsigned long long* out, void* stream);
+int launch_quantize(const float* src, int64_t rows, int64_t row_len, int32_t dtype, void* dst,
+                    float* row_scale, void* stream);
+
+// BF16 / FP8 instantiations (mbdp_kernels_lp_*.hip): null when the shape has
+// none (ELL rows of more than 64 entries).
+typedef void (*SolveFn)(KParams);
+SolveFn pick_dense_lp(const KParams& p);
+SolveFn pick_ell_lp(const KParams& p, int units_per_wave_hint);
+SolveFn pick_band_lp(const KParams& p, int units_per_wave_hint);
 
 }  // namespace mbdp

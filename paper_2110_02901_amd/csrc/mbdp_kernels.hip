@@ -57,6 +57,18 @@ __global__ void csr_inspect_kernel(const int64_t* row_ptr, const int32_t* col, i
     if (row_ptr[0] != 0 || row_ptr[rows] != nnz) atomicAdd(&flags[2], 1ull);
 }
 
+// Transition value i (dense index or CSR entry) as stored, decoded, before the
+// row scale.
+__device__ __forceinline__ float stored_value(const KParams& p, size_t i) {
+  if (p.vdtype == kBF16) return ValBF16::dense_at(p, i);
+  if (p.vdtype == kFP8) return ValFP8::dense_at(p, i);
+  return p.storage == kDense ? p.P[i] : p.val[i];
+}
+
+__device__ __forceinline__ double stored_scale(const KParams& p, int64_t row) {
+  return p.vdtype == kF32 ? 1.0 : (double)p.rscale[row];
+}
+
 // out: [0] bad probability, [1] bad row sum, [2] empty rows, [3] bad column,
 // [4] bad row_ptr, [5] bad cost, [6] no admissible action, [7] max |rowsum-1|
 // (double bits).
@@ -68,9 +80,9 @@ __global__ void validate_kernel(KParams p, double tol, unsigned long long* out) 
        r += (int64_t)gridDim.x * blockDim.x) {
     double s = 0.0;
     if (p.storage == kDense) {
-      const float* row = p.P + (size_t)r * (size_t)p.n;
+      const size_t base = (size_t)r * (size_t)p.n;
       for (int64_t j = 0; j < p.n; ++j) {
-        const float x = row[j];
+        const float x = stored_value(p, base + (size_t)j);
         if (!(x >= 0.f) || isinf(x)) ++bad_p;
         s += (double)x;
       }
@@ -79,13 +91,14 @@ __global__ void validate_kernel(KParams p, double tol, unsigned long long* out) 
       if (e1 < e0) ++bad_ptr;
       if (e1 <= e0) ++empty;
       for (int64_t e = e0; e < e1; ++e) {
-        const float x = p.val[e];
+        const float x = stored_value(p, (size_t)e);
         if (!(x >= 0.f) || isinf(x)) ++bad_p;
         const int32_t cidx = p.col[e];
         if (cidx < 0 || (int64_t)cidx >= p.n) ++bad_col;
         s += (double)x;
       }
     }
+    s *= stored_scale(p, r);
     const double d = fabs(s - 1.0);
     if (!(d <= tol)) ++bad_sum;
     if (d > dev || isnan(d)) dev = isnan(d) ? INFINITY : d;
@@ -109,6 +122,75 @@ __global__ void validate_kernel(KParams p, double tol, unsigned long long* out) 
   if (bad_cost) atomicAdd(&out[5], bad_cost);
   if (no_adm) atomicAdd(&out[6], no_adm);
   if (dev > 0.0) atomicMax(&out[7], (unsigned long long)__double_as_longlong(dev));
+}
+
+// ------------------------------------------------------------ row quantiser
+//
+// BF16: round to nearest even of the FP32 bits.  FP8 E4M3 (OCP E4M3FN: bias
+// 7, subnormals m * 2^-9, largest finite 448, NaN S.1111.111, no infinity):
+// nearest value, ties to the even code, saturating at 448.  Each FP8 row is
+// first multiplied by the power of two 2^(7 - E), E the binary exponent of
+// its largest magnitude (clamped to [-100, 127]), so the scaling is exact and
+// the largest entry lands in [128, 256).  The row scale makes the stored row
+// sum to 1: scale = 1 / sum_j decode(q_j), summed in FP64.
+
+__device__ __forceinline__ unsigned encode_bf16(float x) {
+  const unsigned u = __float_as_uint(x);
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return ((u >> 16) | 0x40u) & 0xFFFFu;
+  return ((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16) & 0xFFFFu;
+}
+
+__device__ __forceinline__ unsigned encode_e4m3(float x) {
+  const unsigned u = __float_as_uint(x);
+  const unsigned sign = (u >> 24) & 0x80u;
+  const unsigned a = u & 0x7FFFFFFFu;
+  if (a > 0x7F800000u) return 0x7Fu | sign;
+  const int e = (int)(a >> 23) - 127;
+  unsigned code;
+  if (e >= -6) {
+    const unsigned keep = ((unsigned)(e + 7) << 3) | ((a >> 20) & 7u);
+    const unsigned rest = a & 0xFFFFFu;
+    const bool up = rest > 0x80000u || (rest == 0x80000u && (keep & 1u));
+    code = keep + (up ? 1u : 0u);
+  } else {
+    code = (unsigned)__builtin_rintf(__builtin_fabsf(x) * 512.0f);  // multiples of 2^-9
+  }
+  return (code < 0x7Eu ? code : 0x7Eu) | sign;
+}
+
+__global__ void quantize_kernel(const float* src, int64_t rows, int64_t len, int32_t dtype,
+                                void* dst, float* scale) {
+  const int lane = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t r = gw; r < rows; r += nw) {
+    const float* row = src + r * len;
+    float alpha = 1.f;
+    if (dtype == kFP8) {
+      float amax = 0.f;
+      for (int64_t j = lane; j < len; j += kWave) amax = fmaxf(amax, fabsf(row[j]));
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+      int e = (int)((__float_as_uint(amax) >> 23) & 0xFFu) - 127;
+      e = e < -100 ? -100 : (e > 127 ? 127 : e);
+      if (amax > 0.f) alpha = __uint_as_float((unsigned)(127 + 7 - e) << 23);
+    }
+    double sum = 0.0;
+    for (int64_t j = lane; j < len; j += kWave) {
+      const float x = row[j] * alpha;
+      if (dtype == kBF16) {
+        const unsigned q = encode_bf16(x);
+        static_cast<uint16_t*>(dst)[r * len + j] = (uint16_t)q;
+        sum += (double)__uint_as_float(q << 16);
+      } else {
+        const unsigned q = encode_e4m3(x);
+        static_cast<uint8_t*>(dst)[r * len + j] = (uint8_t)q;
+        sum += (double)fp8x4(q).x;
+      }
+    }
+    sum = wave_sum_d(sum);
+    if (lane == 0) scale[r] = sum > 0.0 ? (float)(1.0 / sum) : 0.f;
+  }
 }
 
 // ------------------------------------------------------------ launchers
@@ -205,8 +287,9 @@ static int choose(const KParams& p, const LaunchShape& shape, SolveFn* fn, int* 
   const int64_t waves_guess = (int64_t)shape.cus * shape.blocks_per_cu * waves_per_block;
   const int64_t per_wave = waves_guess > 0 ? p.b / waves_guess : 1;
   const int hint = (int)(per_wave > 4 ? 4 : per_wave);
+  const bool lp = p.vdtype != kF32;
   if (p.storage == kEll && p.band >= 0 && !p.perm) {
-    SolveFn fb = pick_band(p, hint);
+    SolveFn fb = lp ? pick_band_lp(p, hint) : pick_band(p, hint);
     if (fb) {
       if (grid_blocks(fb, shape, blocks, err, errlen) != 0) return -1;
       if (band_fits(p, *blocks)) {
@@ -216,7 +299,15 @@ static int choose(const KParams& p, const LaunchShape& shape, SolveFn* fn, int* 
       }
     }
   }
-  *fn = pick(p, hint);
+  if (lp)
+    *fn = p.storage == kDense ? pick_dense_lp(p)
+                              : (p.storage == kEll ? pick_ell_lp(p, hint) : nullptr);
+  else
+    *fn = pick(p, hint);
+  if (!*fn) {
+    snprintf(err, errlen, "no kernel for this storage and value type");
+    return -1;
+  }
   *engine = p.storage == kDense ? kEngineDense : p.storage == kEll ? kEngineEll : kEngineCsr;
   return grid_blocks(*fn, shape, blocks, err, errlen);
 }
@@ -273,6 +364,17 @@ int launch_csr_inspect(const int64_t* row_ptr, const int32_t* col, int64_t rows,
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(csr_inspect_kernel, dim3((unsigned)blocks), dim3(256), 0,
                      reinterpret_cast<hipStream_t>(stream), row_ptr, col, rows, n, nnz, k, flags);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_quantize(const float* src, int64_t rows, int64_t row_len, int32_t dtype, void* dst,
+                    float* row_scale, void* stream) {
+  int64_t blocks = (rows + 3) / 4;  // four rows (waves) per 256-thread block
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(stream), src, rows, row_len, dtype, dst,
+                     row_scale);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

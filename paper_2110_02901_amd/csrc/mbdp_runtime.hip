@@ -33,6 +33,9 @@ struct mbdp_mdp {
   int64_t nnz;
   int32_t ell_k;
   int32_t band;  // kEll: max |s' - s| over the entries of the rows of state s
+  int32_t vdtype;        // kF32, kBF16, kFP8
+  const void* pq;        // BF16 / FP8 values (P or val)
+  const float* rscale;   // BF16 / FP8 per-row scales
   const float* c;
   int device;
   int cus;
@@ -128,6 +131,9 @@ KParams base_params(const mbdp_mdp* h, void* ws, float* V, int64_t b) {
   p.val = h->val;
   p.ell_k = h->ell_k;
   p.band = (h->storage == kEll && h->tuning.band_window >= 0) ? h->band : -1;
+  p.vdtype = h->vdtype;
+  p.pq = h->pq;
+  p.rscale = h->rscale;
   p.c32 = h->c;
   p.vbuf0 = V;
   p.vbuf1 = reinterpret_cast<float*>(base + w.vbuf1);
@@ -195,16 +201,28 @@ extern "C" {
 
 const char* mbdp_last_error(void) { return g_err.c_str(); }
 
-mbdp_status mdp_create_dense(int64_t n, int32_t m, const float* P, const float* c, double gamma,
-                             mbdp_mdp_t* out) {
+}  // extern "C"
+
+namespace {
+
+int values_per_load(int32_t dtype) { return dtype == kBF16 ? 8 : 16; }
+
+bool dtype_ok(int32_t dtype) { return dtype == MBDP_BF16 || dtype == MBDP_FP8_E4M3; }
+
+mbdp_status create_dense(int64_t n, int32_t m, const float* P, const void* Pq, int32_t dtype,
+                         const float* row_scale, const float* c, double gamma, mbdp_mdp_t* out) {
   if (!out) return fail(MBDP_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (n < 1 || n >= kMaxStates) return fail(MBDP_ERR_INVALID_ARG, "n = %lld not in [1, 2^31)", (long long)n);
   if (m < 1) return fail(MBDP_ERR_INVALID_ARG, "m = %d < 1", m);
   if (m > kMaxDenseActions)
     return fail(MBDP_ERR_UNSUPPORTED, "dense storage supports m <= %d (got %d)", kMaxDenseActions, m);
-  if (!P || !c) return fail(MBDP_ERR_INVALID_ARG, "P or c is NULL");
+  if (dtype == kF32 ? !P : (!Pq || !row_scale)) return fail(MBDP_ERR_INVALID_ARG, "P or row_scale is NULL");
+  if (!c) return fail(MBDP_ERR_INVALID_ARG, "c is NULL");
   if (!gamma_ok(gamma)) return fail(MBDP_ERR_INVALID_ARG, "gamma = %g not in (0, 1)", gamma);
+  if (dtype != kF32 && n % values_per_load(dtype) != 0)
+    return fail(MBDP_ERR_UNSUPPORTED, "%s dense rows need n %% %d == 0 (got n = %lld)",
+                dtype == kBF16 ? "BF16" : "FP8", values_per_load(dtype), (long long)n);
   mbdp_mdp* h = new (std::nothrow) mbdp_mdp();
   if (!h) return fail(MBDP_ERR_HIP, "out of host memory");
   h->storage = kDense;
@@ -212,6 +230,9 @@ mbdp_status mdp_create_dense(int64_t n, int32_t m, const float* P, const float* 
   h->m = m;
   h->gamma = gamma;
   h->P = P;
+  h->vdtype = dtype;
+  h->pq = Pq;
+  h->rscale = row_scale;
   h->c = c;
   const mbdp_status st = query_device(h);
   if (st != MBDP_OK) {
@@ -222,16 +243,68 @@ mbdp_status mdp_create_dense(int64_t n, int32_t m, const float* P, const float* 
   return MBDP_OK;
 }
 
+mbdp_status create_csr(int64_t n, int32_t m, const int64_t* row_ptr, const int32_t* col,
+                       const float* val, const void* valq, int32_t dtype, const float* row_scale,
+                       int64_t nnz, const float* c, double gamma, hipStream_t stream,
+                       mbdp_mdp_t* out);
+
+}  // namespace
+
+extern "C" {
+
+mbdp_status mdp_create_dense(int64_t n, int32_t m, const float* P, const float* c, double gamma,
+                             mbdp_mdp_t* out) {
+  return create_dense(n, m, P, nullptr, kF32, nullptr, c, gamma, out);
+}
+
+mbdp_status mdp_create_dense_q(int64_t n, int32_t m, const void* P, int32_t dtype,
+                               const float* row_scale, const float* c, double gamma,
+                               mbdp_mdp_t* out) {
+  if (out) *out = nullptr;
+  if (!dtype_ok(dtype)) return fail(MBDP_ERR_INVALID_ARG, "dtype %d is not BF16 or FP8 E4M3", dtype);
+  return create_dense(n, m, nullptr, P, dtype, row_scale, c, gamma, out);
+}
+
 mbdp_status mdp_create_csr(int64_t n, int32_t m, const int64_t* row_ptr, const int32_t* col,
                            const float* val, int64_t nnz, const float* c, double gamma,
                            hipStream_t stream, mbdp_mdp_t* out) {
+  return create_csr(n, m, row_ptr, col, val, nullptr, kF32, nullptr, nnz, c, gamma, stream, out);
+}
+
+mbdp_status mdp_create_csr_q(int64_t n, int32_t m, const int64_t* row_ptr, const int32_t* col,
+                             const void* val, int32_t dtype, const float* row_scale, int64_t nnz,
+                             const float* c, double gamma, hipStream_t stream, mbdp_mdp_t* out) {
+  if (out) *out = nullptr;
+  if (!dtype_ok(dtype)) return fail(MBDP_ERR_INVALID_ARG, "dtype %d is not BF16 or FP8 E4M3", dtype);
+  return create_csr(n, m, row_ptr, col, nullptr, val, dtype, row_scale, nnz, c, gamma, stream, out);
+}
+
+mbdp_status mdp_quantize_rows(const float* src, int64_t rows, int64_t row_len, int32_t dtype,
+                              void* dst, float* row_scale, hipStream_t stream) {
+  if (!dtype_ok(dtype)) return fail(MBDP_ERR_INVALID_ARG, "dtype %d is not BF16 or FP8 E4M3", dtype);
+  if (rows < 1 || row_len < 1) return fail(MBDP_ERR_INVALID_ARG, "rows and row_len must be >= 1");
+  if (!src || !dst || !row_scale) return fail(MBDP_ERR_INVALID_ARG, "src, dst or row_scale is NULL");
+  if (launch_quantize(src, rows, row_len, dtype, dst, row_scale, stream) != 0)
+    return fail(MBDP_ERR_HIP, "quantize launch failed: %s", hipGetErrorString(hipGetLastError()));
+  return MBDP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+mbdp_status create_csr(int64_t n, int32_t m, const int64_t* row_ptr, const int32_t* col,
+                       const float* val, const void* valq, int32_t dtype, const float* row_scale,
+                       int64_t nnz, const float* c, double gamma, hipStream_t stream,
+                       mbdp_mdp_t* out) {
   if (!out) return fail(MBDP_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (n < 1 || n >= kMaxStates) return fail(MBDP_ERR_INVALID_ARG, "n = %lld not in [1, 2^31)", (long long)n);
   if (m < 1) return fail(MBDP_ERR_INVALID_ARG, "m = %d < 1", m);
   if (nnz < 0) return fail(MBDP_ERR_INVALID_ARG, "nnz = %lld < 0", (long long)nnz);
-  if (!row_ptr || !c || (nnz > 0 && (!col || !val)))
-    return fail(MBDP_ERR_INVALID_ARG, "row_ptr, col, val or c is NULL");
+  const bool have_vals = dtype == kF32 ? val != nullptr : (valq != nullptr && row_scale != nullptr);
+  if (!row_ptr || !c || (nnz > 0 && (!col || !have_vals)))
+    return fail(MBDP_ERR_INVALID_ARG, "row_ptr, col, val, row_scale or c is NULL");
   if (!gamma_ok(gamma)) return fail(MBDP_ERR_INVALID_ARG, "gamma = %g not in (0, 1)", gamma);
   mbdp_mdp* h = new (std::nothrow) mbdp_mdp();
   if (!h) return fail(MBDP_ERR_HIP, "out of host memory");
@@ -242,6 +315,9 @@ mbdp_status mdp_create_csr(int64_t n, int32_t m, const int64_t* row_ptr, const i
   h->row_ptr = row_ptr;
   h->col = col;
   h->val = val;
+  h->vdtype = dtype;
+  h->pq = valq;
+  h->rscale = row_scale;
   h->nnz = nnz;
   h->c = c;
   mbdp_status st = query_device(h);
@@ -284,9 +360,18 @@ mbdp_status mdp_create_csr(int64_t n, int32_t m, const int64_t* row_ptr, const i
     h->ell_k = (int32_t)k;
     h->band = (int32_t)flags[4];
   }
+  if (dtype != kF32 && !(h->storage == kEll && k <= 64)) {
+    delete h;
+    return fail(MBDP_ERR_UNSUPPORTED,
+                "BF16 / FP8 values need a constant row length k with k %% 4 == 0, 4 <= k <= 64");
+  }
   *out = h;
   return MBDP_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 mbdp_status mdp_destroy(mbdp_mdp_t h) {
   delete h;
