@@ -100,6 +100,9 @@ def main():
     ap.add_argument("--batch-sizes", default=None,
                     help="comma-separated batch sizes (default: the workload's)")
     ap.add_argument("--eps", type=float, default=1e-6)
+    ap.add_argument("--precision", default="f32", choices=["f32", "bf16", "fp8"],
+                    help="storage of the transition probabilities (BF16 / FP8 rows with one "
+                         "scale per row, quantised on the GPU; the solve targets the stored MDP)")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mpi", action="store_true")
@@ -159,8 +162,24 @@ def main():
         bytes_per_backup = 8 * wl["k"] + 4  # k (column, weight) pairs + the cost
     log("generated and uploaded %s (%.2f GB) in %.1f s"
         % (wl_name, nbytes / 1e9, time.perf_counter() - t0))
-    ws = mb.workspace(h, n)
     stream = torch.cuda.current_stream()
+    h32 = h
+    if args.precision != "f32":
+        # BF16 / FP8 rows with one scale per row, quantised by the library
+        t0 = time.perf_counter()
+        vbytes = 2 if args.precision == "bf16" else 1
+        rows = Pd.reshape(n * m, n) if dense else dev_arrays[2].reshape(n * m, wl["k"])
+        codes, rscale = mb.mdp_quantize_rows(rows, args.precision)
+        torch.cuda.synchronize()
+        if dense:
+            h = mb.mdp_create_dense_q(codes.reshape(-1), args.precision, rscale, cd, gamma)
+            bytes_per_backup = vbytes * n + 8  # one row, its scale and its cost
+        else:
+            h = mb.mdp_create_csr_q(dev_arrays[0], dev_arrays[1], codes.reshape(-1),
+                                    args.precision, rscale, dev_arrays[3], gamma)
+            bytes_per_backup = (4 + vbytes) * wl["k"] + 8
+        log("quantised to %s in %.1f s" % (args.precision, time.perf_counter() - t0))
+    ws = mb.workspace(h, n)
 
     if args.profile_sweeps:
         b = batch_sizes[0]
@@ -194,6 +213,15 @@ def main():
         raise RuntimeError("reference solve did not converge: %s" % st)
     log("reference: %d sweeps, %d improvements, residual %.3g, %.1f s"
         % (st["sweeps"], st["outer_iters"], st["final_dv_inf"], time.perf_counter() - t0))
+    if h32 is not h:
+        # the FP32 MDP's own solution, for the error of the stored MDP's
+        Vref32 = torch.zeros(n, dtype=torch.float64, device=dev)
+        st = mb.mpi_solve(h32, Vtmp, pol, 20, n, 999, ws, policy_is_init=False, tol_dv=1e-11,
+                          max_outer=2000, V64_out=Vref32)
+        if not st["converged"]:
+            raise RuntimeError("FP32 reference solve did not converge: %s" % st)
+        lp_err = float((Vref - Vref32).abs().max())
+        log("%s storage: max|J*(stored) - J*(FP32)| = %.3g" % (args.precision, lp_err))
 
     V = torch.zeros(n, dtype=torch.float32, device=dev)
 
@@ -249,8 +277,54 @@ def main():
     backups = total_sweeps * n * m
     value = backups / wall
     kernel_gbps = backups * bytes_per_backup / total_s / 1e9
-    traffic = committed_traffic(wl_name, best_b, total_sweeps / args.steps)
+    traffic = committed_traffic(wl_name if args.precision == "f32"
+                                else "%s-%s" % (wl_name, args.precision),
+                                best_b, total_sweeps / args.steps)
     engine = mb.mdp_engine(h, best_b)
+
+    precision = None
+    if h32 is not h:
+        # the stored MDP's solution as a warm start for FP32 sweeps to eps of
+        # the FP32 MDP: the time the reduced precision saves at equal accuracy
+        V.zero_()
+        V64 = torch.zeros(n, dtype=torch.float64, device=dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s1 = mb.vi_solve(h, V, best_b, seed, ws, tol_dv=-1.0, eps=args.eps, V_ref=Vref,
+                         max_sweeps=20000, V64_out=V64)
+        e1.record(stream)
+        s2 = mb.vi_solve(h32, V, best_b, seed, ws, tol_dv=-1.0, eps=args.eps, V_ref=Vref32,
+                         max_sweeps=20000, first_sweep=s1["sweeps"])
+        e2.record(stream)
+        e2.synchronize()
+        V.zero_()
+        s3 = mb.vi_solve(h32, V, best_b, seed, ws, tol_dv=-1.0, eps=args.eps, V_ref=Vref32,
+                         max_sweeps=20000)
+        torch.cuda.synchronize()
+        t_f32 = None
+        e3 = torch.cuda.Event(enable_timing=True)
+        e4 = torch.cuda.Event(enable_timing=True)
+        V.zero_()
+        e3.record(stream)
+        mb.vi_solve(h32, V, best_b, seed, ws, tol_dv=-1.0, eps=args.eps, V_ref=Vref32,
+                    max_sweeps=20000)
+        e4.record(stream)
+        e4.synchronize()
+        t_f32 = e3.elapsed_time(e4)
+        precision = {
+            "storage": args.precision,
+            "err_stored_vs_f32_solution": lp_err,
+            "stored_solve": {"sweeps": s1["sweeps"], "ms": e0.elapsed_time(e1)},
+            "f32_finish_from_stored": {"sweeps": s2["sweeps"], "ms": e1.elapsed_time(e2),
+                                       "converged": bool(s2["converged"])},
+            "f32_alone": {"sweeps": s3["sweeps"], "ms": t_f32},
+        }
+        log("%s: stored-MDP solve %d sweeps %.1f ms, FP32 finish %d sweeps %.1f ms; "
+            "FP32 alone %d sweeps %.1f ms" % (args.precision, s1["sweeps"], e0.elapsed_time(e1),
+                                              s2["sweeps"], e1.elapsed_time(e2), s3["sweeps"],
+                                              t_f32))
 
     line = {
         "metric": METRIC,
@@ -263,11 +337,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32",  # arithmetic; the storage of P is config.storage
         "data": "synthetic",
         "config": dict({"workload": wl_name, "n": n, "m": m, "alpha": wl["alpha"],
                         "gamma": gamma, "solver": "vi", "b": best_b, "eps": args.eps,
-                        "perm_seed": seed, "data_seed": wl["data_seed"]},
+                        "perm_seed": seed, "data_seed": wl["data_seed"],
+                        "storage": args.precision},
                        **({} if dense else {"k": wl["k"], "band": wl["band"]})),
         "hbm_gbps": kernel_gbps,
         "time_to_eps": {
@@ -290,6 +365,8 @@ def main():
             "algorithmic_bytes_per_backup": bytes_per_backup,
         },
     }
+    if precision:
+        line["precision"] = precision
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (~%.0f s)" % args.cpu_baseline_seconds)
         import oracle

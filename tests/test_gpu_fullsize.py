@@ -83,6 +83,29 @@ def test_dense_8192x16_mpi_reaches_eps(c2):
     assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= out_tol(1e-6, Vstar)
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_dense_8192x16_lowprec_sweep(c2, dtype):
+    """BF16 / FP8 storage at full size: one sweep at b = 1024 against the
+    oracle on the stored MDP (codes and scales from the oracle's quantiser;
+    the library's codes must equal them)."""
+    from oracle import quantize as qz
+    wl, h32, mdp32, _ = c2
+    n, m = wl["n"], wl["m"]
+    P32 = mdp32.P.reshape(n * m, n)
+    t0 = time.time()
+    q_ref, s_ref = qz.quantize_rows(P32, dtype)
+    q_gpu, s_gpu = mb.mdp_quantize_rows(up(P32), dtype)
+    torch.cuda.synchronize()
+    assert np.array_equal(q_gpu.cpu().numpy().view(q_ref.dtype), q_ref)
+    assert np.all(np.abs(s_gpu.cpu().numpy() - s_ref) <= np.spacing(s_ref))
+    h = mb.mdp_create_dense_q(q_gpu.reshape(-1), dtype, s_gpu, up(mdp32.c), wl["gamma"])
+    mdp = oracle.DenseMDP(qz.dequantized(q_ref, s_ref, dtype).reshape(n, m, n), mdp32.c,
+                          wl["gamma"])
+    say("%s codes checked in %.1f s" % (dtype, time.time() - t0))
+    V0 = inputs.values(n, 24, 5.8, 6.4)
+    run_sweep(h, mdp, V0, 1024, wl["perm_seed"], 0, check_arg=False)
+
+
 def _sparse(name):
     wl = inputs.WORKLOADS[name]
     t0 = time.time()
@@ -114,6 +137,25 @@ def test_sparse_1M_policy_sweep(c3):
     wl, h, mdp = c3
     V0 = inputs.values(wl["n"], 22, 21.0, 23.0)
     run_sweep(h, mdp, V0, 65536, wl["perm_seed"], 1, policy=inputs.policy(wl["n"], wl["m"], 23))
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_sparse_1M_lowprec_sweep(c3, dtype):
+    from oracle import quantize as qz
+    wl, h32, mdp32 = c3
+    n, m, k = wl["n"], wl["m"], wl["k"]
+    rows = mdp32.val.reshape(n * m, k)
+    q_ref, s_ref = qz.quantize_rows(rows, dtype)
+    q_gpu, s_gpu = mb.mdp_quantize_rows(up(rows), dtype)
+    torch.cuda.synchronize()
+    assert np.array_equal(q_gpu.cpu().numpy().view(q_ref.dtype), q_ref)
+    h = mb.mdp_create_csr_q(up(mdp32.row_ptr), up(mdp32.col), q_gpu.reshape(-1), dtype, s_gpu,
+                            up(mdp32.c), wl["gamma"])
+    mdp = oracle.CsrMDP(mdp32.row_ptr, mdp32.col, qz.dequantized(q_ref, s_ref, dtype).reshape(-1),
+                        mdp32.c, wl["gamma"])
+    say("%s storage, engine at b = 65536: %s" % (dtype, mb.mdp_engine(h, 65536)))
+    V0 = inputs.values(n, 25, 21.0, 23.0)
+    run_sweep(h, mdp, V0, 65536, wl["perm_seed"], 0, check_arg=False)
 
 
 def test_sparse_1M_vi_certified_eps(c3):
