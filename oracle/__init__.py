@@ -20,6 +20,9 @@ Lygeros; arXiv 2110.02901):
                      policy iteration (Algorithm 1), exact policy evaluation
                      (eq. (4)), Howard policy iteration and brute-force
                      enumeration of J* (eq. (2)).
+* ``adjoint``     -- gradients of L = w^T J* with respect to the costs and the
+                     stored transition values at the optimal policy, via the
+                     adjoint equation (I - gamma P_mu)^T lambda = w.
 * ``quantize``    -- BF16 / FP8 E4M3 storage of transition rows with one
                      scale per row renormalising it to sum 1 (the reduced-
                      precision variant; the paper fixes no precision).
