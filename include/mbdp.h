@@ -150,6 +150,33 @@ mbdp_status mdp_create_csr_q(int64_t n, int32_t m, const int64_t* row_ptr, const
                              const void* val, int32_t dtype, const float* row_scale, int64_t nnz,
                              const float* c, double gamma, hipStream_t stream, mbdp_mdp_t* out);
 
+/* Differentiation (an extension: the paper stops at J*).  For L = g^T J*
+ * with a unique optimal policy mu, J* = (I - gamma P_mu)^-1 c_mu near the
+ * data (eq. (4)), so with the adjoint lambda = (I - gamma P_mu)^-T g:
+ *   dL/dc(s, a) = lambda(s) [a == mu(s)],
+ *   dL/dP(s, a, s') = gamma lambda(s) J*(s') [a == mu(s)]
+ * (partial derivatives with respect to the stored entries).  The adjoint
+ * equation lambda = g + gamma P_mu^T lambda is a policy evaluation on the
+ * transposed policy rows: mdp_policy_transpose writes P_mu^T as CSR arrays
+ * (row_ptr_t int64[n+1], col_t int32[n*k], val_t FP32[n*k], each row in
+ * increasing source state; all device, caller-allocated) and a handle made
+ * from them with mdp_create_csr (m = 1, costs g, the same gamma) solves it
+ * with vi_solve: the same mini-batch sweep, on the transpose.  Both calls
+ * need an FP32 handle with constant row length k (else
+ * MBDP_ERR_UNSUPPORTED), use the workspace of mdp_workspace_bytes(h, 1),
+ * reject policy entries outside [0, m) (MBDP_ERR_INVALID_ARG) and
+ * synchronise `stream`. */
+mbdp_status mdp_policy_transpose(mbdp_mdp_t h, const int32_t* policy, int64_t* row_ptr_t,
+                                 int32_t* col_t, float* val_t, void* workspace, size_t ws_bytes,
+                                 hipStream_t stream);
+
+/* grad_c FP64[n*m] and grad_val FP64[n*m*k] (either may be NULL) from the
+ * policy, the adjoint lambda FP64[n] and J* FP64[n] by the formulas above;
+ * entries of rows that mu does not select get 0. */
+mbdp_status mdp_value_gradients(mbdp_mdp_t h, const int32_t* policy, const double* lambda,
+                                const double* V, double* grad_c, double* grad_val,
+                                void* workspace, size_t ws_bytes, hipStream_t stream);
+
 /* Replaces the handle's tuning knobs. */
 mbdp_status mdp_set_tuning(mbdp_mdp_t h, const mbdp_tuning* t);
 

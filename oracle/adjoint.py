@@ -21,9 +21,11 @@ import numpy as np
 from .bellman import CsrMDP, DenseMDP, _policy_matrix
 
 
-def adjoint(mdp, mu, w):
+def adjoint(mdp, mu, w, iterative_tol=None):
     """lambda solving (I - gamma P_mu)^T lambda = w (FP64): LAPACK for dense
-    storage, sparse LU for CSR."""
+    storage, sparse LU for CSR, or -- when ``iterative_tol`` is given --
+    BiCGSTAB to that relative residual (for large random sparse matrices,
+    whose LU fills in)."""
     n = mdp.n
     Pm = _policy_matrix(mdp, mu)
     w = np.asarray(w, dtype=np.float64)
@@ -31,18 +33,23 @@ def adjoint(mdp, mu, w):
         return np.linalg.solve((np.eye(n) - mdp.gamma * Pm).T, w)
     import scipy.sparse as sp
     import scipy.sparse.linalg as spla
-    A = (sp.identity(n, format="csr") - mdp.gamma * Pm).T.tocsc()
-    return spla.spsolve(A, w)
+    A = (sp.identity(n, format="csr") - mdp.gamma * Pm).T.tocsr()
+    if iterative_tol is None:
+        return spla.spsolve(A.tocsc(), w)
+    x, info = spla.bicgstab(A, w, rtol=iterative_tol, atol=0.0, maxiter=100000)
+    if info != 0:
+        raise RuntimeError("BiCGSTAB did not converge (info=%d)" % info)
+    return x
 
 
-def value_gradients(mdp, mu, V, w):
+def value_gradients(mdp, mu, V, w, iterative_tol=None):
     """(lambda, dL/dc [n, m], dL/dP) for L = w^T V at the policy mu with
     V = J_mu.  dL/dP has P's shape for dense storage and one entry per stored
     value for CSR storage."""
     n, m = mdp.n, mdp.m
     mu = np.asarray(mu, dtype=np.int64)
     V = np.asarray(V, dtype=np.float64)
-    lam = adjoint(mdp, mu, w)
+    lam = adjoint(mdp, mu, w, iterative_tol)
     gc = np.zeros((n, m))
     gc[np.arange(n), mu] = lam
     if isinstance(mdp, DenseMDP):

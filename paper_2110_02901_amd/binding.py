@@ -37,7 +37,8 @@ STATUS_NAMES = {
 # Every symbol include/mbdp.h declares.
 EXPORTS = [
     "mdp_create_dense", "mdp_create_csr", "mdp_create_dense_q", "mdp_create_csr_q",
-    "mdp_quantize_rows", "mdp_destroy", "mdp_set_tuning",
+    "mdp_quantize_rows", "mdp_policy_transpose", "mdp_value_gradients", "mdp_destroy",
+    "mdp_set_tuning",
     "mdp_workspace_bytes", "mdp_engine", "mdp_validate", "mbdp_permutation", "mb_sweep",
     "mbdp_sync_status", "vi_solve", "mpi_solve", "mbdp_last_error",
 ]
@@ -93,6 +94,8 @@ _SIGS = {
     "mdp_create_csr_q": (_I32, [_I64, _I32, _P, _P, _P, _I32, _P, _I64, _P, _D, _P,
                                 ctypes.POINTER(_P)]),
     "mdp_quantize_rows": (_I32, [_P, _I64, _I64, _I32, _P, _P, _P]),
+    "mdp_policy_transpose": (_I32, [_P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "mdp_value_gradients": (_I32, [_P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "mdp_set_tuning": (_I32, [_P, ctypes.POINTER(Tuning)]),
     "mdp_workspace_bytes": (ctypes.c_size_t, [_P, _I64]),
     "mdp_engine": (_I32, [_P, _I64, ctypes.POINTER(ctypes.c_char_p)]),
@@ -255,6 +258,35 @@ def mdp_create_csr_q(row_ptr, col, valq, dtype, row_scale, c, gamma, stream=None
                                   _ptr(row_scale), col.numel(), _ptr(c), float(gamma),
                                   _stream(stream), ctypes.byref(h)))
     return Handle(h, n, m, (row_ptr, col, valq, row_scale, c))
+
+
+def mdp_policy_transpose(h, policy, k, ws, stream=None):
+    """P_mu^T of an ELL handle as device CSR arrays (row_ptr, col, val)."""
+    import torch
+    n = h.n
+    _require(policy, torch.int32, n, "policy")
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=policy.device)
+    col = torch.empty(n * k, dtype=torch.int32, device=policy.device)
+    val = torch.empty(n * k, dtype=torch.float32, device=policy.device)
+    _check(lib().mdp_policy_transpose(h.ptr, _ptr(policy), _ptr(row_ptr), _ptr(col), _ptr(val),
+                                      _ptr(ws), ws.numel(), _stream(stream)))
+    return row_ptr, col, val
+
+
+def mdp_value_gradients(h, policy, lam, V, ws, grad_c=True, grad_val=True, k=None, stream=None):
+    """(dL/dc FP64 [n*m] or None, dL/dval FP64 [n*m*k] or None)."""
+    import torch
+    n, m = h.n, h.m
+    _require(policy, torch.int32, n, "policy")
+    _require(lam, torch.float64, n, "lambda")
+    _require(V, torch.float64, n, "V")
+    gc = torch.empty(n * m, dtype=torch.float64, device=V.device) if grad_c else None
+    gv = torch.empty(n * m * k, dtype=torch.float64, device=V.device) if grad_val else None
+    _check(lib().mdp_value_gradients(h.ptr, _ptr(policy), _ptr(lam), _ptr(V),
+                                     _ptr(gc) if gc is not None else None,
+                                     _ptr(gv) if gv is not None else None,
+                                     _ptr(ws), ws.numel(), _stream(stream)))
+    return gc, gv
 
 
 def mdp_destroy(h):

@@ -165,6 +165,12 @@ int launch_csr_inspect(const int64_t* row_ptr, const int32_t* col, int64_t rows,
 int launch_validate(const KParams& p, double tol, unsigned long long* out, void* stream);
 int launch_quantize(const float* src, int64_t rows, int64_t row_len, int32_t dtype, void* dst,
                     float* row_scale, void* stream);
+// scratch: (64 + 2 n) words, zeroed; scratch[0] counts bad policy entries
+int launch_policy_transpose(const KParams& p, const int32_t* policy, int64_t* row_ptr_t,
+                            int32_t* col_t, float* val_t, unsigned* scratch, void* stream);
+int launch_value_gradients(const KParams& p, const int32_t* policy, const double* lambda,
+                           const double* V, double* grad_c, double* grad_val, unsigned* flags,
+                           void* stream);
 
 // BF16 / FP8 instantiations (mbdp_kernels_lp_*.hip): null when the shape has
 // none (ELL rows of more than 64 entries).

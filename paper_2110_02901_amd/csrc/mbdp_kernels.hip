@@ -193,6 +193,120 @@ __global__ void quantize_kernel(const float* src, int64_t rows, int64_t len, int
   }
 }
 
+// ------------------------------------------------------------ adjoint
+//
+// The adjoint equation (I - gamma P_mu)^T lambda = g of L = g^T J* is a
+// policy evaluation on the transposed policy rows: lambda = g + gamma
+// P_mu^T lambda.  These kernels build P_mu^T in CSR form from the ELL rows
+// (s, mu(s)): in-degree counts, an exclusive scan, a scatter, and a sort of
+// each transposed row by source state so the result does not depend on the
+// order of the scatter's atomics.  flags[0] counts policy entries outside
+// [0, m).
+
+__device__ __forceinline__ int policy_action(const KParams& p, const int32_t* policy, int64_t s,
+                                             unsigned* flags) {
+  int a = policy[s];
+  if (a < 0 || a >= p.m) {
+    atomicAdd(&flags[0], 1u);
+    a = 0;
+  }
+  return a;
+}
+
+__global__ void adj_count_kernel(KParams p, const int32_t* policy, unsigned* cnt,
+                                 unsigned* flags) {
+  const int64_t k = p.ell_k;
+  const int64_t total = p.n * k;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = i / k;
+    const int a = policy_action(p, policy, s, flags);
+    atomicAdd(&cnt[p.col[(s * p.m + a) * k + i % k]], 1u);
+  }
+}
+
+// row_ptr[0..n] <- exclusive prefix sums of cnt[0..n) (one workgroup).
+__global__ void adj_scan_kernel(const unsigned* cnt, int64_t n, int64_t* row_ptr) {
+  __shared__ int64_t part[1024];
+  const int64_t nt = blockDim.x, per = (n + nt - 1) / nt;
+  const int64_t i0 = min(n, (int64_t)threadIdx.x * per), i1 = min(n, i0 + per);
+  int64_t sum = 0;
+  for (int64_t i = i0; i < i1; ++i) sum += cnt[i];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+      const int64_t v = part[t];
+      part[t] = run;
+      run += v;
+    }
+    row_ptr[n] = run;
+  }
+  __syncthreads();
+  int64_t run = part[threadIdx.x];
+  for (int64_t i = i0; i < i1; ++i) {
+    row_ptr[i] = run;
+    run += cnt[i];
+  }
+}
+
+__global__ void adj_fill_kernel(KParams p, const int32_t* policy, const int64_t* row_ptr,
+                                unsigned* cursor, int32_t* col_t, float* val_t, unsigned* flags) {
+  const int64_t k = p.ell_k;
+  const int64_t total = p.n * k;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = i / k;
+    const int a = policy_action(p, policy, s, flags);
+    const int64_t e = (s * p.m + a) * k + i % k;
+    const int32_t j = p.col[e];
+    const int64_t pos = row_ptr[j] + atomicAdd(&cursor[j], 1u);
+    col_t[pos] = (int32_t)s;
+    val_t[pos] = p.val[e];
+  }
+}
+
+// Each transposed row in increasing source state (insertion sort; rows hold
+// a few dozen entries).
+__global__ void adj_sort_kernel(const int64_t* row_ptr, int64_t n, int32_t* col_t, float* val_t) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e0 = row_ptr[j], e1 = row_ptr[j + 1];
+    for (int64_t e = e0 + 1; e < e1; ++e) {
+      const int32_t c = col_t[e];
+      const float v = val_t[e];
+      int64_t f = e - 1;
+      while (f >= e0 && col_t[f] > c) {
+        col_t[f + 1] = col_t[f];
+        val_t[f + 1] = val_t[f];
+        --f;
+      }
+      col_t[f + 1] = c;
+      val_t[f + 1] = v;
+    }
+  }
+}
+
+// grad_c[s*m+a] = lambda(s) [a == mu(s)]; grad_val[e] = gamma lambda(s) V(col[e])
+// on the entries of row (s, mu(s)), 0 on the other rows.
+__global__ void adj_grad_kernel(KParams p, const int32_t* policy, const double* lambda,
+                                const double* V, double* grad_c, double* grad_val,
+                                unsigned* flags) {
+  const int64_t k = p.ell_k, m = p.m;
+  const int64_t rows = p.n * m;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = r / m;
+    const bool on = (r % m) == policy_action(p, policy, s, flags);
+    const double ls = lambda[s];
+    if (grad_c) grad_c[r] = on ? ls : 0.0;
+    if (grad_val)
+      for (int64_t e = r * k; e < (r + 1) * k; ++e)
+        grad_val[e] = on ? p.gamma * ls * V[p.col[e]] : 0.0;
+  }
+}
+
 // ------------------------------------------------------------ launchers
 
 // Result words of the CSR structure inspection done by mdp_create_csr (the
@@ -375,6 +489,40 @@ int launch_quantize(const float* src, int64_t rows, int64_t row_len, int32_t dty
   hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)blocks), dim3(256), 0,
                      reinterpret_cast<hipStream_t>(stream), src, rows, row_len, dtype, dst,
                      row_scale);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+static unsigned grid_for(int64_t work) {
+  int64_t blocks = (work + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  return (unsigned)blocks;
+}
+
+int launch_policy_transpose(const KParams& p, const int32_t* policy, int64_t* row_ptr_t,
+                            int32_t* col_t, float* val_t, unsigned* scratch, void* stream) {
+  // scratch: flags[1] (padded to 64 words), counts[n], cursors[n]; zeroed by the caller
+  const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  unsigned* flags = scratch;
+  unsigned* cnt = scratch + 64;
+  unsigned* cursor = cnt + p.n;
+  const int64_t total = p.n * p.ell_k;
+  hipLaunchKernelGGL(adj_count_kernel, dim3(grid_for(total)), dim3(256), 0, st, p, policy, cnt,
+                     flags);
+  hipLaunchKernelGGL(adj_scan_kernel, dim3(1), dim3(1024), 0, st, cnt, p.n, row_ptr_t);
+  hipLaunchKernelGGL(adj_fill_kernel, dim3(grid_for(total)), dim3(256), 0, st, p, policy,
+                     row_ptr_t, cursor, col_t, val_t, flags);
+  hipLaunchKernelGGL(adj_sort_kernel, dim3(grid_for(p.n)), dim3(256), 0, st, row_ptr_t, p.n,
+                     col_t, val_t);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_value_gradients(const KParams& p, const int32_t* policy, const double* lambda,
+                           const double* V, double* grad_c, double* grad_val, unsigned* flags,
+                           void* stream) {
+  hipLaunchKernelGGL(adj_grad_kernel, dim3(grid_for(p.n * p.m)), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(stream), p, policy, lambda, V, grad_c,
+                     grad_val, flags);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

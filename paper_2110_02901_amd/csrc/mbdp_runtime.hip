@@ -410,6 +410,55 @@ mbdp_status mdp_engine(mbdp_mdp_t h, int64_t b, const char** name) {
   return MBDP_OK;
 }
 
+mbdp_status mdp_policy_transpose(mbdp_mdp_t h, const int32_t* policy, int64_t* row_ptr_t,
+                                 int32_t* col_t, float* val_t, void* workspace, size_t ws_bytes,
+                                 hipStream_t stream) {
+  if (!h) return fail(MBDP_ERR_INVALID_ARG, "handle is NULL");
+  if (!policy || !row_ptr_t || !col_t || !val_t)
+    return fail(MBDP_ERR_INVALID_ARG, "policy, row_ptr_t, col_t or val_t is NULL");
+  if (h->storage != kEll || h->vdtype != kF32)
+    return fail(MBDP_ERR_UNSUPPORTED,
+                "the policy transpose needs FP32 rows of constant length (ELL storage)");
+  mbdp_status st = check_ws(h, workspace, ws_bytes);
+  if (st != MBDP_OK) return st;
+  const size_t scratch = (64 + 2 * (size_t)h->n) * sizeof(unsigned);
+  if (launch_zero(workspace, scratch, stream) != 0)
+    return fail(MBDP_ERR_HIP, "clear failed: %s", hipGetErrorString(hipGetLastError()));
+  KParams p = base_params(h, workspace, nullptr, 1);
+  if (launch_policy_transpose(p, policy, row_ptr_t, col_t, val_t,
+                              static_cast<unsigned*>(workspace), stream) != 0)
+    return fail(MBDP_ERR_HIP, "transpose launch failed: %s", hipGetErrorString(hipGetLastError()));
+  unsigned bad = 0;
+  MBDP_HIP(hipMemcpyAsync(&bad, workspace, sizeof bad, hipMemcpyDeviceToHost, stream));
+  MBDP_HIP(hipStreamSynchronize(stream));
+  if (bad) return fail(MBDP_ERR_INVALID_ARG, "%u policy entries outside [0, m)", bad);
+  return MBDP_OK;
+}
+
+mbdp_status mdp_value_gradients(mbdp_mdp_t h, const int32_t* policy, const double* lambda,
+                                const double* V, double* grad_c, double* grad_val,
+                                void* workspace, size_t ws_bytes, hipStream_t stream) {
+  if (!h) return fail(MBDP_ERR_INVALID_ARG, "handle is NULL");
+  if (!policy || !lambda || !V) return fail(MBDP_ERR_INVALID_ARG, "policy, lambda or V is NULL");
+  if (!grad_c && !grad_val) return fail(MBDP_ERR_INVALID_ARG, "grad_c and grad_val are NULL");
+  if (h->storage != kEll || h->vdtype != kF32)
+    return fail(MBDP_ERR_UNSUPPORTED,
+                "value gradients need FP32 rows of constant length (ELL storage)");
+  mbdp_status st = check_ws(h, workspace, ws_bytes);
+  if (st != MBDP_OK) return st;
+  if (launch_zero(workspace, 256, stream) != 0)
+    return fail(MBDP_ERR_HIP, "clear failed: %s", hipGetErrorString(hipGetLastError()));
+  KParams p = base_params(h, workspace, nullptr, 1);
+  if (launch_value_gradients(p, policy, lambda, V, grad_c, grad_val,
+                             static_cast<unsigned*>(workspace), stream) != 0)
+    return fail(MBDP_ERR_HIP, "gradient launch failed: %s", hipGetErrorString(hipGetLastError()));
+  unsigned bad = 0;
+  MBDP_HIP(hipMemcpyAsync(&bad, workspace, sizeof bad, hipMemcpyDeviceToHost, stream));
+  MBDP_HIP(hipStreamSynchronize(stream));
+  if (bad) return fail(MBDP_ERR_INVALID_ARG, "%u policy entries outside [0, m)", bad);
+  return MBDP_OK;
+}
+
 mbdp_status mdp_validate(mbdp_mdp_t h, double row_sum_tol, void* workspace, size_t ws_bytes,
                          hipStream_t stream, mbdp_validation* report) {
   if (!h) return fail(MBDP_ERR_INVALID_ARG, "handle is NULL");

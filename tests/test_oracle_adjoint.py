@@ -104,3 +104,12 @@ def test_transpose_policy_rows_matches_scipy():
     assert np.array_equal(T, ref)
     for j in range(50):
         assert np.all(np.diff(col[rp[j]:rp[j + 1]]) > 0)
+
+
+def test_iterative_adjoint_matches_sparse_lu():
+    mdp = _csr(500, 3, 10, 17, 0.98)
+    mu = np.random.Generator(np.random.Philox(6)).integers(0, 3, 500)
+    w = _w(500, 7)
+    direct = adj.adjoint(mdp, mu, w)
+    iterative = adj.adjoint(mdp, mu, w, iterative_tol=1e-13)
+    assert np.max(np.abs(direct - iterative)) <= 1e-10 * np.max(np.abs(direct))
