@@ -177,6 +177,57 @@ mbdp_status mdp_value_gradients(mbdp_mdp_t h, const int32_t* policy, const doubl
                                 const double* V, double* grad_c, double* grad_val,
                                 void* workspace, size_t ws_bytes, hipStream_t stream);
 
+/* Batching (an extension: many independent dense MDPs of uneven size in
+ * one launch).  Each MDP is solved by MB-VI (Sec. III-B) on one workgroup:
+ * its own sweep orders (seed), batch size b and stop rule, V in LDS, FP64
+ * arithmetic on FP32 / BF16 / FP8 rows (decoded exactly), so its iterates
+ * are the FP64 MB-VI iterates of the stored MDP.  Workgroups take MDPs from
+ * a queue, largest first. */
+typedef struct {
+  int64_t n;              /* states, 1 <= n <= 8192 */
+  int32_t m;              /* actions, 1 <= m <= 64 */
+  int32_t dtype;          /* MBDP_F32, MBDP_BF16 or MBDP_FP8_E4M3 */
+  int64_t ld;             /* row stride of P in values: >= n, <= 8192, a multiple of 16 */
+  const void* P;          /* device, [n][m][ld], 16-byte aligned, padding columns zero */
+  const float* row_scale; /* device [n*m] (BF16 / FP8; see mdp_quantize_rows), else NULL */
+  const float* c;         /* device [n][m] */
+  double gamma;           /* in (0, 1) */
+  int64_t b;              /* batch size, 1 <= b <= min(n, 4096) */
+  uint64_t seed;          /* sweep orders sigma_t of this MDP */
+  double* V;              /* device [n]: V0 in, the last iterate out */
+  int32_t* policy;        /* device [n]: greedy policy at the last iterate, or NULL */
+  int32_t lanes;          /* lanes per state: 16, 32 or 64; 0 picks by row length */
+  int32_t reserved;
+} mbdp_batch_item;
+
+typedef struct {
+  int64_t sweeps;
+  double final_dv_inf;    /* max |dV| of the last sweep */
+  int32_t converged;      /* final_dv_inf <= tol_dv */
+  int32_t reserved;
+} mbdp_batch_stats;
+
+/* Workspace bytes of a batch of `count` MDPs (0 if count < 1). */
+size_t mdp_batch_workspace_bytes(int32_t count);
+
+/* Checks the items and writes the item table (ordered by work, largest
+ * first) into the workspace; synchronises `stream`.  Pointers are borrowed
+ * until the last launch using them has finished. */
+mbdp_status mdp_batch_upload(const mbdp_batch_item* items, int32_t count, void* workspace,
+                             size_t ws_bytes, hipStream_t stream);
+
+/* Runs every uploaded MDP to max |dV| <= tol_dv or max_sweeps sweeps.
+ * Enqueues kernels only (no copies, no synchronisation, no allocation), so
+ * it can be captured in a hipGraph and replayed; V is read at the start of
+ * each launch. */
+mbdp_status mdp_batch_launch(int32_t count, double tol_dv, int64_t max_sweeps, void* workspace,
+                             size_t ws_bytes, hipStream_t stream);
+
+/* Statistics of the last launch, in the order of the uploaded items;
+ * synchronises `stream`. */
+mbdp_status mdp_batch_read_stats(void* workspace, int32_t count, mbdp_batch_stats* out,
+                                 hipStream_t stream);
+
 /* Replaces the handle's tuning knobs. */
 mbdp_status mdp_set_tuning(mbdp_mdp_t h, const mbdp_tuning* t);
 

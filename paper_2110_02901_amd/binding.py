@@ -38,7 +38,8 @@ STATUS_NAMES = {
 EXPORTS = [
     "mdp_create_dense", "mdp_create_csr", "mdp_create_dense_q", "mdp_create_csr_q",
     "mdp_quantize_rows", "mdp_policy_transpose", "mdp_value_gradients", "mdp_destroy",
-    "mdp_set_tuning",
+    "mdp_set_tuning", "mdp_batch_workspace_bytes", "mdp_batch_upload", "mdp_batch_launch",
+    "mdp_batch_read_stats",
     "mdp_workspace_bytes", "mdp_engine", "mdp_validate", "mbdp_permutation", "mb_sweep",
     "mbdp_sync_status", "vi_solve", "mpi_solve", "mbdp_last_error",
 ]
@@ -75,6 +76,19 @@ class Validation(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("ld", ctypes.c_int64), ("P", ctypes.c_void_p), ("row_scale", ctypes.c_void_p),
+                ("c", ctypes.c_void_p), ("gamma", ctypes.c_double), ("b", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("V", ctypes.c_void_p), ("policy", ctypes.c_void_p),
+                ("lanes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("final_dv_inf", ctypes.c_double),
+                ("converged", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_int32), ("threads_per_block", ctypes.c_int32),
                 ("recentre_every", ctypes.c_int32), ("recentre_force", ctypes.c_int32),
@@ -95,6 +109,10 @@ _SIGS = {
                                 ctypes.POINTER(_P)]),
     "mdp_quantize_rows": (_I32, [_P, _I64, _I64, _I32, _P, _P, _P]),
     "mdp_policy_transpose": (_I32, [_P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "mdp_batch_workspace_bytes": (ctypes.c_size_t, [_I32]),
+    "mdp_batch_upload": (_I32, [ctypes.POINTER(BatchItem), _I32, _P, ctypes.c_size_t, _P]),
+    "mdp_batch_launch": (_I32, [_I32, _D, _I64, _P, ctypes.c_size_t, _P]),
+    "mdp_batch_read_stats": (_I32, [_P, _I32, ctypes.POINTER(BatchStats), _P]),
     "mdp_value_gradients": (_I32, [_P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "mdp_set_tuning": (_I32, [_P, ctypes.POINTER(Tuning)]),
     "mdp_workspace_bytes": (ctypes.c_size_t, [_P, _I64]),
@@ -287,6 +305,47 @@ def mdp_value_gradients(h, policy, lam, V, ws, grad_c=True, grad_val=True, k=Non
                                      _ptr(gv) if gv is not None else None,
                                      _ptr(ws), ws.numel(), _stream(stream)))
     return gc, gv
+
+
+_BATCH_DTYPES = {"f32": MBDP_F32, "bf16": MBDP_BF16, "fp8": MBDP_FP8_E4M3}
+
+
+def batch_workspace(count):
+    """A torch uint8 workspace for a batch of `count` MDPs (256-byte aligned)."""
+    import torch
+    nbytes = int(lib().mdp_batch_workspace_bytes(int(count)))
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + nbytes]
+
+
+def mdp_batch_upload(items, ws, stream=None):
+    """items: list of dicts with n, m, dtype ('f32' / 'bf16' / 'fp8'), ld, P,
+    row_scale (or None), c, gamma, b, seed, V (FP64, V0 in / result out),
+    policy (int32 or None), lanes (0 = default).  The tensors must stay
+    alive while launches use them."""
+    arr = (BatchItem * len(items))()
+    for i, it in enumerate(items):
+        arr[i] = BatchItem(int(it["n"]), int(it["m"]), _BATCH_DTYPES[it.get("dtype", "f32")],
+                           int(it["ld"]), it["P"].data_ptr(),
+                           it["row_scale"].data_ptr() if it.get("row_scale") is not None else None,
+                           it["c"].data_ptr(), float(it["gamma"]), int(it["b"]),
+                           int(it.get("seed", 0)), it["V"].data_ptr(),
+                           it["policy"].data_ptr() if it.get("policy") is not None else None,
+                           int(it.get("lanes", 0)), 0)
+    _check(lib().mdp_batch_upload(arr, len(items), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def mdp_batch_launch(count, tol_dv, max_sweeps, ws, stream=None):
+    _check(lib().mdp_batch_launch(int(count), float(tol_dv), int(max_sweeps), _ptr(ws),
+                                  ws.numel(), _stream(stream)))
+
+
+def mdp_batch_read_stats(ws, count, stream=None):
+    out = (BatchStats * count)()
+    _check(lib().mdp_batch_read_stats(_ptr(ws), int(count), out, _stream(stream)))
+    return [{"sweeps": o.sweeps, "final_dv_inf": o.final_dv_inf, "converged": o.converged}
+            for o in out]
 
 
 def mdp_destroy(h):

@@ -172,6 +172,51 @@ int launch_value_gradients(const KParams& p, const int32_t* policy, const double
                            const double* V, double* grad_c, double* grad_val, unsigned* flags,
                            void* stream);
 
+// Many small dense MDPs solved in one launch (mbdp_batch.hip): a workgroup
+// per MDP, V in LDS, FP64 arithmetic.
+constexpr int64_t kBatchMaxN = 8192;  // states (and row stride) per MDP
+constexpr int64_t kBatchMaxB = 4096;  // batch size per MDP
+constexpr int32_t kBatchMaxM = 64;    // actions per MDP
+
+struct BatchItem {
+  int64_t n, ld, b;
+  int32_t m, dtype;
+  const void* P;
+  const float* rscale;
+  const float* c;
+  double gamma;
+  uint64_t seed;
+  double* V;
+  int32_t* policy;
+  int32_t lanes;   // lanes per state: 16, 32 or 64
+  int32_t index;   // position in the caller's list (results go there)
+};
+
+struct BatchStat {
+  long long sweeps;
+  double dv;
+  int converged;
+  int pad;
+};
+
+// Workspace of a batched solve: queue counter (cleared per launch), the
+// item table, the statistics.
+struct BatchLayout {
+  size_t queue, items, stats, total;
+};
+inline BatchLayout batch_layout(int32_t count) {
+  BatchLayout l{};
+  size_t off = 0;
+  l.queue = off;  off = align_up(off + 256, 256);
+  l.items = off;  off = align_up(off + (size_t)count * sizeof(BatchItem), 256);
+  l.stats = off;  off = align_up(off + (size_t)count * sizeof(BatchStat), 256);
+  l.total = off;
+  return l;
+}
+
+int launch_batch(const BatchItem* items, int count, unsigned* queue, BatchStat* stats, double tol,
+                 long long max_sweeps, int blocks, void* stream);
+
 // BF16 / FP8 instantiations (mbdp_kernels_lp_*.hip): null when the shape has
 // none (ELL rows of more than 64 entries).
 typedef void (*SolveFn)(KParams);

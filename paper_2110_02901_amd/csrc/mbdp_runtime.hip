@@ -12,9 +12,11 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "mbdp.h"
 #include "mbdp_internal.h"
@@ -456,6 +458,118 @@ mbdp_status mdp_value_gradients(mbdp_mdp_t h, const int32_t* policy, const doubl
   MBDP_HIP(hipMemcpyAsync(&bad, workspace, sizeof bad, hipMemcpyDeviceToHost, stream));
   MBDP_HIP(hipStreamSynchronize(stream));
   if (bad) return fail(MBDP_ERR_INVALID_ARG, "%u policy entries outside [0, m)", bad);
+  return MBDP_OK;
+}
+
+size_t mdp_batch_workspace_bytes(int32_t count) {
+  if (count < 1) return 0;
+  return batch_layout(count).total;
+}
+
+mbdp_status mdp_batch_upload(const mbdp_batch_item* items, int32_t count, void* workspace,
+                             size_t ws_bytes, hipStream_t stream) {
+  if (count < 1 || !items) return fail(MBDP_ERR_INVALID_ARG, "need count >= 1 items");
+  const BatchLayout L = batch_layout(count);
+  if (!workspace || ((uintptr_t)workspace) % 256 || ws_bytes < L.total)
+    return fail(MBDP_ERR_WORKSPACE, "batch workspace must be 256-byte aligned with %zu bytes",
+                L.total);
+  std::vector<BatchItem> table((size_t)count);
+  std::vector<double> work((size_t)count);
+  for (int32_t i = 0; i < count; ++i) {
+    const mbdp_batch_item& it = items[i];
+    if (it.n < 1 || it.n > kBatchMaxN)
+      return fail(MBDP_ERR_INVALID_ARG, "item %d: n = %lld not in [1, %lld]", i,
+                  (long long)it.n, (long long)kBatchMaxN);
+    if (it.m < 1 || it.m > kBatchMaxM)
+      return fail(MBDP_ERR_INVALID_ARG, "item %d: m = %d not in [1, %d]", i, it.m, kBatchMaxM);
+    if (it.ld < it.n || it.ld % 16 != 0 || it.ld > kBatchMaxN)
+      return fail(MBDP_ERR_INVALID_ARG, "item %d: ld = %lld must be >= n, <= %lld and a multiple of 16",
+                  i, (long long)it.ld, (long long)kBatchMaxN);
+    if (it.b < 1 || it.b > it.n || it.b > kBatchMaxB)
+      return fail(MBDP_ERR_INVALID_ARG, "item %d: b = %lld not in [1, min(n, %lld)]", i,
+                  (long long)it.b, (long long)kBatchMaxB);
+    if (!gamma_ok(it.gamma)) return fail(MBDP_ERR_INVALID_ARG, "item %d: gamma not in (0, 1)", i);
+    if (it.dtype != MBDP_F32 && it.dtype != MBDP_BF16 && it.dtype != MBDP_FP8_E4M3)
+      return fail(MBDP_ERR_INVALID_ARG, "item %d: unknown dtype %d", i, it.dtype);
+    if (!it.P || !it.c || !it.V || (it.dtype != MBDP_F32 && !it.row_scale))
+      return fail(MBDP_ERR_INVALID_ARG, "item %d: P, c, V or row_scale is NULL", i);
+    if (((uintptr_t)it.P) % 16)
+      return fail(MBDP_ERR_INVALID_ARG, "item %d: P must be 16-byte aligned", i);
+    if (it.lanes != 0 && it.lanes != 16 && it.lanes != 32 && it.lanes != 64)
+      return fail(MBDP_ERR_INVALID_ARG, "item %d: lanes must be 0, 16, 32 or 64", i);
+    BatchItem& b = table[(size_t)i];
+    b.n = it.n;
+    b.ld = it.ld;
+    b.b = it.b;
+    b.m = it.m;
+    b.dtype = it.dtype;
+    b.P = it.P;
+    b.rscale = it.row_scale;
+    b.c = it.c;
+    b.gamma = it.gamma;
+    b.seed = it.seed;
+    b.V = it.V;
+    b.policy = it.policy;
+    // default lane group: a step of the group should cover about a row
+    const int epl = it.dtype == MBDP_F32 ? 4 : (it.dtype == MBDP_BF16 ? 8 : 16);
+    b.lanes = it.lanes ? it.lanes : (it.ld >= 64 * epl ? 64 : (it.ld >= 32 * epl ? 32 : 16));
+    b.index = i;
+    // work estimate: bytes per sweep times sweeps to shrink the error 1e6-fold
+    const double bytes = (double)it.n * it.m * it.ld * (it.dtype == MBDP_F32 ? 4 : it.dtype == MBDP_BF16 ? 2 : 1);
+    work[(size_t)i] = bytes * (13.8 / -log(it.gamma));
+  }
+  // largest first, so the long solves start early and small ones fill in
+  std::vector<int32_t> order((size_t)count);
+  for (int32_t i = 0; i < count; ++i) order[(size_t)i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return work[(size_t)x] > work[(size_t)y]; });
+  std::vector<BatchItem> sorted((size_t)count);
+  for (int32_t i = 0; i < count; ++i) sorted[(size_t)i] = table[(size_t)order[(size_t)i]];
+  char* base = static_cast<char*>(workspace);
+  MBDP_HIP(hipMemcpyAsync(base + L.items, sorted.data(), sorted.size() * sizeof(BatchItem),
+                          hipMemcpyHostToDevice, stream));
+  MBDP_HIP(hipStreamSynchronize(stream));
+  return MBDP_OK;
+}
+
+mbdp_status mdp_batch_launch(int32_t count, double tol_dv, int64_t max_sweeps, void* workspace,
+                             size_t ws_bytes, hipStream_t stream) {
+  if (count < 1) return fail(MBDP_ERR_INVALID_ARG, "count must be >= 1");
+  if (max_sweeps < 1) return fail(MBDP_ERR_INVALID_ARG, "max_sweeps must be >= 1");
+  const BatchLayout L = batch_layout(count);
+  if (!workspace || ((uintptr_t)workspace) % 256 || ws_bytes < L.total)
+    return fail(MBDP_ERR_WORKSPACE, "batch workspace must be 256-byte aligned with %zu bytes",
+                L.total);
+  int device = 0, cus = 0;
+  MBDP_HIP(hipGetDevice(&device));
+  MBDP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+  char* base = static_cast<char*>(workspace);
+  // kernels only (a fill kernel clears the queue), so the call can be captured
+  if (launch_zero(base + L.queue, 256, stream) != 0)
+    return fail(MBDP_ERR_HIP, "clear failed: %s", hipGetErrorString(hipGetLastError()));
+  const int blocks = cus < count ? cus : count;
+  if (launch_batch(reinterpret_cast<const BatchItem*>(base + L.items), count,
+                   reinterpret_cast<unsigned*>(base + L.queue),
+                   reinterpret_cast<BatchStat*>(base + L.stats), tol_dv, (long long)max_sweeps,
+                   blocks, stream) != 0)
+    return fail(MBDP_ERR_HIP, "batch launch failed: %s", hipGetErrorString(hipGetLastError()));
+  return MBDP_OK;
+}
+
+mbdp_status mdp_batch_read_stats(void* workspace, int32_t count, mbdp_batch_stats* out,
+                                 hipStream_t stream) {
+  if (count < 1 || !workspace || !out) return fail(MBDP_ERR_INVALID_ARG, "bad arguments");
+  const BatchLayout L = batch_layout(count);
+  std::vector<BatchStat> st((size_t)count);
+  MBDP_HIP(hipMemcpyAsync(st.data(), static_cast<char*>(workspace) + L.stats,
+                          st.size() * sizeof(BatchStat), hipMemcpyDeviceToHost, stream));
+  MBDP_HIP(hipStreamSynchronize(stream));
+  for (int32_t i = 0; i < count; ++i) {
+    out[i].sweeps = st[(size_t)i].sweeps;
+    out[i].final_dv_inf = st[(size_t)i].dv;
+    out[i].converged = st[(size_t)i].converged;
+    out[i].reserved = 0;
+  }
   return MBDP_OK;
 }
 

@@ -1,0 +1,153 @@
+"""GPU parity of the batched solve (many independent dense MDPs in one
+launch) against the oracle: each MDP's iterate after a fixed number of
+sweeps equals the oracle's FP64 MB-VI from the same V0, seed and batch size
+(the kernel computes in FP64 too), the greedy policies, the limit J*, and
+replays of a hipGraph-captured launch."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import quantize as qz
+from paper_2110_02901_amd import binding as mb
+from paper_2110_02901_amd import inputs
+
+from gpu_util import check_argmin, dev, up
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print("[batch] " + msg, flush=True)
+
+
+def make_item(n, m, dtype, gamma, b, seed, data_seed, lanes=0, alpha=1.0, with_oracle=True):
+    """(item dict for the library, oracle MDP of the stored rows or None, V0)."""
+    ld = (n + 15) // 16 * 16
+    P, c = inputs.dense_mdp(n, m, alpha, data_seed, dtype=np.float32)
+    Ppad = np.zeros((n, m, ld), dtype=np.float32)
+    Ppad[:, :, :n] = P
+    rows = up(Ppad.reshape(n * m, ld))
+    Pstored = None
+    if dtype == "f32":
+        Pd, scale = rows, None
+        if with_oracle:
+            Pstored = P.astype(np.float64)
+    else:
+        Pd, scale = mb.mdp_quantize_rows(rows, dtype)
+        del rows
+        if with_oracle:
+            q_ref, s_ref = qz.quantize_rows(Ppad.reshape(n * m, ld), dtype)
+            Pstored = qz.dequantized(q_ref, s_ref, dtype).reshape(n, m, ld)[:, :, :n]
+    V0 = inputs.values(n, data_seed + 1000, 0.0, 2.0, dtype=np.float64)
+    item = {"n": n, "m": m, "dtype": dtype, "ld": ld, "P": Pd, "row_scale": scale,
+            "c": up(c), "gamma": gamma, "b": b, "seed": seed,
+            "V": up(V0.copy()), "policy": torch.zeros(n, dtype=torch.int32, device=dev()),
+            "lanes": lanes}
+    return item, (oracle.DenseMDP(Pstored, c, gamma) if with_oracle else (Ppad, c)), V0
+
+
+def mixed_batch():
+    specs = [(16, 3, "f32", 0.9, 4, 0), (100, 5, "bf16", 0.85, 13, 16), (256, 8, "fp8", 0.95, 32, 32),
+             (333, 2, "f32", 0.93, 42, 64), (700, 8, "bf16", 0.9, 88, 0), (64, 1, "fp8", 0.8, 64, 16),
+             (500, 10, "f32", 0.97, 63, 32), (1000, 4, "fp8", 0.9, 125, 64), (7, 2, "bf16", 0.5, 3, 16),
+             (900, 8, "f32", 0.99, 113, 0)]
+    out = []
+    for i, (n, m, dt, g, b, lanes) in enumerate(specs):
+        out.append(make_item(n, m, dt, g, b, 500 + i, 40 + i, lanes))
+    return out
+
+
+def test_batch_iterates_match_oracle_after_fixed_sweeps():
+    batch = mixed_batch()
+    items = [x[0] for x in batch]
+    ws = mb.batch_workspace(len(items))
+    mb.mdp_batch_upload(items, ws)
+    T = 25
+    mb.mdp_batch_launch(len(items), -1.0, T, ws)
+    stats = mb.mdp_batch_read_stats(ws, len(items))
+    for (item, mdp, V0), st in zip(batch, stats):
+        assert st["sweeps"] == T and not st["converged"]
+        ref, _, _ = oracle.value_iteration(mdp, item["b"], item["seed"], V0=V0, tol_dv=-1,
+                                           max_sweeps=T)
+        Vg = item["V"].cpu().numpy()
+        err = float(np.max(np.abs(Vg - ref)))
+        say("n=%d m=%d %s b=%d lanes=%d: max err %.3g" % (item["n"], item["m"], item["dtype"],
+                                                         item["b"], item["lanes"], err))
+        assert err <= 1e-11 * max(1.0, float(np.max(np.abs(ref))))
+        Q = oracle.q_values(mdp, np.arange(mdp.n), Vg)
+        check_argmin(Q, item["policy"].cpu().numpy(), 1e-10)
+
+
+def test_batch_solves_reach_the_limit():
+    batch = mixed_batch()
+    items = [x[0] for x in batch]
+    ws = mb.batch_workspace(len(items))
+    mb.mdp_batch_upload(items, ws)
+    mb.mdp_batch_launch(len(items), 1e-11, 100000, ws)
+    stats = mb.mdp_batch_read_stats(ws, len(items))
+    for (item, mdp, _), st in zip(batch, stats):
+        assert st["converged"], st
+        Vs, _, _ = oracle.policy_iteration(mdp, improve_tol=1e-14)
+        bound = 1e-11 * item["gamma"] / (1 - item["gamma"]) + 1e-12 * float(np.max(np.abs(Vs)))
+        assert np.max(np.abs(item["V"].cpu().numpy() - Vs)) <= 10 * bound
+
+
+def test_batch_launch_replays_from_a_hip_graph():
+    batch = mixed_batch()[:6]
+    items = [x[0] for x in batch]
+    V0s = [x[2] for x in batch]
+    ws = mb.batch_workspace(len(items))
+    mb.mdp_batch_upload(items, ws)
+    T = 12
+    # eager reference
+    mb.mdp_batch_launch(len(items), -1.0, T, ws)
+    torch.cuda.synchronize()
+    eager = [it["V"].clone() for it in items]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        for it, V0 in zip(items, V0s):
+            it["V"].copy_(up(V0))
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=s):
+            mb.mdp_batch_launch(len(items), -1.0, T, ws)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for it, V0 in zip(items, V0s):
+            it["V"].copy_(up(V0))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for it, ref in zip(items, eager):
+            assert torch.equal(it["V"], ref), rep
+        # eager work between replays
+        _ = torch.ones(1000, device=dev()).sum().item()
+
+
+def test_batch_at_scale_sampled():
+    """32 MDPs with n ~ U[256, 2048], m = 8, BF16, gamma ~ U[0.9, 0.99],
+    b = ceil(n / 8): a fixed number of sweeps, three MDPs against the oracle."""
+    g = np.random.Generator(np.random.Philox(77))
+    count = 32
+    ns = g.integers(256, 2049, count)
+    gammas = g.uniform(0.9, 0.99, count)
+    check = {int(np.argmax(ns)), int(np.argmin(ns)), 7}
+    batch = [make_item(int(n), 8, "bf16", float(gm), int((n + 7) // 8), 900 + i, 300 + i,
+                       with_oracle=(i in check))
+             for i, (n, gm) in enumerate(zip(ns, gammas))]
+    items = [x[0] for x in batch]
+    ws = mb.batch_workspace(count)
+    mb.mdp_batch_upload(items, ws)
+    T = 10
+    mb.mdp_batch_launch(count, -1.0, T, ws)
+    stats = mb.mdp_batch_read_stats(ws, count)
+    assert all(st["sweeps"] == T for st in stats)
+    for i in sorted(check):
+        item, mdp, V0 = batch[i]
+        ref, _, _ = oracle.value_iteration(mdp, item["b"], item["seed"], V0=V0, tol_dv=-1,
+                                           max_sweeps=T)
+        err = float(np.max(np.abs(item["V"].cpu().numpy() - ref)))
+        say("item %d n=%d: max err %.3g" % (i, item["n"], err))
+        assert err <= 1e-11 * max(1.0, float(np.max(np.abs(ref))))
