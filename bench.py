@@ -90,13 +90,119 @@ def cpu_baseline(mdp, wl_name, b, seed, budget_s=20.0):
                       "%.1f s" % (sweeps, b, wl_name, n, m, dt)}
 
 
+def run_batch(args, dev):
+    """512 independent dense MDPs, n ~ U[256, 4096], m = 8, Dirichlet(1) rows in
+    BF16 with one scale per row, c ~ U[0, 1), gamma ~ U[0.9, 0.99], b =
+    ceil(n / 8), all solved in one launch (replayed from a hipGraph) until
+    max |dV| <= 1e-8 (so max |V - J*| <= 1e-8 gamma / (1 - gamma) < 1e-6).
+    The MDPs are drawn on the GPU (torch's seeded generator)."""
+    import torch
+    from paper_2110_02901_amd import binding as mb
+    from paper_2110_02901_amd import tune
+
+    count, m, tol = 512, 8, 1e-8
+    g = np.random.Generator(np.random.Philox(104))
+    ns = g.integers(256, 4097, count)
+    gammas = g.uniform(0.9, 0.99, count)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(104)
+    t0 = time.perf_counter()
+    items = []
+    total_bytes = 0
+    for i in range(count):
+        n = int(ns[i])
+        ld = (n + 15) // 16 * 16
+        rows = torch.zeros(n * m, ld, dtype=torch.float32, device=dev)
+        w = torch._standard_gamma(torch.ones(n * m, n, device=dev), generator=gen)
+        rows[:, :n] = w / w.sum(dim=1, keepdim=True)
+        del w
+        codes, scale = mb.mdp_quantize_rows(rows, "bf16")
+        del rows
+        c = torch.rand(n, m, device=dev, generator=gen)
+        items.append({"n": n, "m": m, "dtype": "bf16", "ld": ld, "P": codes.reshape(-1),
+                      "row_scale": scale, "c": c, "gamma": float(gammas[i]),
+                      "b": (n + 7) // 8, "seed": 2000 + i,
+                      "V": torch.zeros(n, dtype=torch.float64, device=dev), "policy": None,
+                      "lanes": 0})
+        total_bytes += n * m * (2 * ld + 8)
+    torch.cuda.synchronize()
+    log("generated %d MDPs (%.1f GB of BF16 rows) in %.1f s"
+        % (count, total_bytes / 1e9, time.perf_counter() - t0))
+    tuned = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        tuned = tune.tune_lanes(items)
+        log("lane widths tuned in %.1f s: %s" % (time.perf_counter() - t0,
+            {"%s/%d" % k: v[0] for k, v in tuned.items()}))
+    ws = mb.batch_workspace(count)
+    mb.mdp_batch_upload(items, ws)
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            mb.mdp_batch_launch(count, tol, 1000000, ws)
+    torch.cuda.current_stream().wait_stream(stream)
+
+    def step():
+        for it in items:
+            it["V"].zero_()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        graph.replay()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    for _ in range(args.warmup):
+        step()
+    kernel_s = 0.0
+    wall = 0.0
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        kernel_s += step()
+        wall += time.perf_counter() - t0
+    stats = mb.mdp_batch_read_stats(ws, count)
+    if not all(st["converged"] for st in stats):
+        raise RuntimeError("batch did not converge")
+    backups = sum(st["sweeps"] * int(ns[i]) * m for i, st in enumerate(stats))
+    bytes_step = sum(st["sweeps"] * int(ns[i]) * m * (2 * items[i]["ld"] + 8)
+                     for i, st in enumerate(stats))
+    gbps = bytes_step * args.steps / kernel_s / 1e9
+    sweeps = [st["sweeps"] for st in stats]
+    log("batch: %d MDPs, sweeps %d..%d (mean %.0f), %.1f ms per solve of all"
+        % (count, min(sweeps), max(sweeps), float(np.mean(sweeps)), kernel_s / args.steps * 1e3))
+    line = {
+        "metric": METRIC, "value": backups * args.steps / wall, "unit": "backups/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batch-512", "count": count, "n": "U[256, 4096]", "m": m,
+                   "alpha": 1.0, "gamma": "U[0.9, 0.99]", "b": "ceil(n / 8)",
+                   "storage": "bf16", "tol_dv": tol, "launch": "hipGraph replay"},
+        "hbm_gbps": gbps,
+        "sweeps": {"min": min(sweeps), "max": max(sweeps), "mean": float(np.mean(sweeps))},
+        "lanes": None if tuned is None else {"%s/%d" % k: v[0] for k, v in tuned.items()},
+        "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "batch_kernel (a workgroup per MDP)",
+                     "algorithmic_bytes_per_backup": "2 ld + 8"},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dense-8192x16",
-                    choices=["dense-8192x16", "csr-1M-banded", "csr-1M-uniform"])
+                    choices=["dense-8192x16", "csr-1M-banded", "csr-1M-uniform", "batch-512"])
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batch-512: keep the default lane-group widths")
     ap.add_argument("--batch-sizes", default=None,
                     help="comma-separated batch sizes (default: the workload's)")
     ap.add_argument("--eps", type=float, default=1e-6)
@@ -138,6 +244,9 @@ def main():
                           "copy_probe_bytes_written": y.numel() * 4, "launches": 3}))
         return
     wl_name = args.workload
+    if wl_name == "batch-512":
+        run_batch(args, dev)
+        return
     wl = inputs.WORKLOADS[wl_name]
     n, m, gamma = wl["n"], wl["m"], wl["gamma"]
     seed = wl["perm_seed"]
