@@ -182,7 +182,12 @@ mbdp_status mdp_value_gradients(mbdp_mdp_t h, const int32_t* policy, const doubl
  * its own sweep orders (seed), batch size b and stop rule, V in LDS, FP64
  * arithmetic on FP32 / BF16 / FP8 rows (decoded exactly), so its iterates
  * are the FP64 MB-VI iterates of the stored MDP.  Workgroups take MDPs from
- * a queue, largest first. */
+ * a queue, heaviest first.  An MDP much heavier than the rest (bytes per
+ * sweep times the sweeps its gamma needs, against the total over the
+ * device's compute units) is served by a team of workgroups that split each
+ * batch and exchange its new values through device memory; the iterates are
+ * the same.  The members of all teams together must fit on the device at
+ * once (one workgroup per compute unit). */
 typedef struct {
   int64_t n;              /* states, 1 <= n <= 8192 */
   int32_t m;              /* actions, 1 <= m <= 64 */
@@ -197,7 +202,7 @@ typedef struct {
   double* V;              /* device [n]: V0 in, the last iterate out */
   int32_t* policy;        /* device [n]: greedy policy at the last iterate, or NULL */
   int32_t lanes;          /* lanes per state: 16, 32 or 64; 0 picks by row length */
-  int32_t reserved;
+  int32_t team;           /* workgroups serving the MDP, 1..16; 0 picks by work */
 } mbdp_batch_item;
 
 typedef struct {
@@ -210,9 +215,11 @@ typedef struct {
 /* Workspace bytes of a batch of `count` MDPs (0 if count < 1). */
 size_t mdp_batch_workspace_bytes(int32_t count);
 
-/* Checks the items and writes the item table (ordered by work, largest
- * first) into the workspace; synchronises `stream`.  Pointers are borrowed
- * until the last launch using them has finished. */
+/* Checks the items, sizes the teams for the current device and writes the
+ * item table (teams first, then by work per workgroup, heaviest first) into
+ * the workspace; synchronises `stream`.  Explicit team sizes that do not fit
+ * on the device give MBDP_ERR_UNSUPPORTED; automatic ones are reduced.
+ * Pointers are borrowed until the last launch using them has finished. */
 mbdp_status mdp_batch_upload(const mbdp_batch_item* items, int32_t count, void* workspace,
                              size_t ws_bytes, hipStream_t stream);
 
@@ -224,7 +231,9 @@ mbdp_status mdp_batch_launch(int32_t count, double tol_dv, int64_t max_sweeps, v
                              size_t ws_bytes, hipStream_t stream);
 
 /* Statistics of the last launch, in the order of the uploaded items;
- * synchronises `stream`. */
+ * synchronises `stream`.  MBDP_ERR_DEVICE if a team barrier gave up (a team
+ * member did not arrive within 60 s; the launch then stops early and the
+ * statistics are incomplete). */
 mbdp_status mdp_batch_read_stats(void* workspace, int32_t count, mbdp_batch_stats* out,
                                  hipStream_t stream);
 

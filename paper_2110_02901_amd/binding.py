@@ -81,7 +81,7 @@ class BatchItem(ctypes.Structure):
                 ("ld", ctypes.c_int64), ("P", ctypes.c_void_p), ("row_scale", ctypes.c_void_p),
                 ("c", ctypes.c_void_p), ("gamma", ctypes.c_double), ("b", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("V", ctypes.c_void_p), ("policy", ctypes.c_void_p),
-                ("lanes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lanes", ctypes.c_int32), ("team", ctypes.c_int32)]
 
 
 class BatchStats(ctypes.Structure):
@@ -322,7 +322,7 @@ def batch_workspace(count):
 def mdp_batch_upload(items, ws, stream=None):
     """items: list of dicts with n, m, dtype ('f32' / 'bf16' / 'fp8'), ld, P,
     row_scale (or None), c, gamma, b, seed, V (FP64, V0 in / result out),
-    policy (int32 or None), lanes (0 = default).  The tensors must stay
+    policy (int32 or None), lanes (0 = default), team (workgroups; 0 = by work).  The tensors must stay
     alive while launches use them."""
     arr = (BatchItem * len(items))()
     for i, it in enumerate(items):
@@ -332,7 +332,7 @@ def mdp_batch_upload(items, ws, stream=None):
                            it["c"].data_ptr(), float(it["gamma"]), int(it["b"]),
                            int(it.get("seed", 0)), it["V"].data_ptr(),
                            it["policy"].data_ptr() if it.get("policy") is not None else None,
-                           int(it.get("lanes", 0)), 0)
+                           int(it.get("lanes", 0)), int(it.get("team", 0)))
     _check(lib().mdp_batch_upload(arr, len(items), _ptr(ws), ws.numel(), _stream(stream)))
 
 

@@ -1,13 +1,22 @@
 // Many independent dense MDPs of uneven size in one launch.
 //
-// A workgroup takes the next MDP from a queue (largest first, ordered on the
-// host) and runs MB-VI on it alone: the sweep order sigma_t of its own n and
-// seed, batches of its own b, and between batches only a workgroup barrier,
-// since no other workgroup touches the MDP.  V (FP64, up to 8192 states)
-// lives in LDS for the whole solve; the rows stream from HBM, FP32 / BF16 /
-// FP8 values decoded exactly and accumulated in FP64, so no re-centring is
-// needed.  The launch is an ordinary one (no cooperative barrier) and can
-// be captured in a hipGraph.
+// A workgroup takes the next MDP from a queue and runs MB-VI on it alone:
+// the sweep order sigma_t of its own n and seed, batches of its own b, and
+// between batches only a workgroup barrier, since no other workgroup
+// touches the MDP.  V (FP64, up to 8192 states) lives in LDS for the whole
+// solve; the rows stream from HBM, FP32 / BF16 / FP8 values decoded exactly
+// and accumulated in FP64, so no re-centring is needed.  The launch is an
+// ordinary one (no cooperative launch) and can be captured in a hipGraph.
+//
+// The heaviest MDPs (bytes per sweep times the sweeps gamma asks for) are
+// served by a team of workgroups instead, so that one long solve does not
+// hold the whole launch on one compute unit: the members split each batch's
+// states, publish the new values in a global buffer, meet at a team barrier
+// (an arrival counter), and each copies the batch into its own LDS V.  The
+// queue hands out the teams' tickets first and the host keeps the members of
+// all teams within the compute units of the device, so every member of every
+// team is resident from the start and no member waits for a workgroup that
+// is busy with another MDP.
 //
 // A lane group of LANES lanes serves one state at a time: lanes split the
 // row's columns, 16 bytes of the row per lane and step, and the rows of the
@@ -89,7 +98,7 @@ struct BatchShared {
   double newv[kBatchMaxB];
   int32_t sidx[kBatchMaxB];
   double red[16];
-  int item;
+  int item, rank, ok;
 };
 
 // min_a Q(s, a) (FP64) and its action, lowest index on ties, for the lane
@@ -218,43 +227,197 @@ __device__ void batch_solve_item(const BatchItem& I, BatchShared& sh, BatchStat*
   __syncthreads();
 }
 
-template <int VT>
-__device__ __forceinline__ void batch_dispatch_lanes(const BatchItem& I, BatchShared& sh,
-                                                     BatchStat* stats, double tol,
-                                                     long long max_sweeps) {
-  if (I.lanes == 16)
-    batch_solve_item<VT, 16>(I, sh, stats, tol, max_sweeps);
-  else if (I.lanes == 32)
-    batch_solve_item<VT, 32>(I, sh, stats, tol, max_sweeps);
-  else
-    batch_solve_item<VT, 64>(I, sh, stats, tol, max_sweeps);
+// Team of K workgroups on one MDP (see the file comment).  The arrival
+// counter only grows: the p-th barrier of the solve (p = 0, 1, ...) ends when
+// it reaches (p + 1) K.  Release by one thread after every wave's memory
+// operations are done makes the workgroup's writes visible device-wide;
+// acquire after the wait makes the others' writes visible to it.  Gives up
+// (false, and raises the launch's abort flag) after `timeout` ticks or when
+// another team gave up.
+__device__ __forceinline__ bool team_sync(unsigned long long* arrive, unsigned* abort,
+                                          unsigned long long target,
+                                          unsigned long long timeout, BatchShared& sh) {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's loads and stores are done
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(arrive, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    const unsigned long long t0 = wall_clock64();
+    while (atomic_load_agent(arrive) < target) {
+      if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        ok = 0;
+        break;
+      }
+      if (wall_clock64() - t0 > timeout) {
+        __hip_atomic_store(abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    sh.ok = ok;
+  }
+  __syncthreads();
+  return sh.ok != 0;
 }
 
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)))
-batch_kernel(const BatchItem* items, int count, unsigned* queue, BatchStat* stats, double tol,
-             long long max_sweeps) {
-  __shared__ BatchShared sh;
-  while (true) {
-    if (threadIdx.x == 0) sh.item = (int)atomicAdd(queue, 1u);
-    __syncthreads();
-    const int it = sh.item;
-    __syncthreads();
-    if (it >= count) break;
-    const BatchItem I = items[it];
-    if (I.dtype == kBF16)
-      batch_dispatch_lanes<kBF16>(I, sh, stats, tol, max_sweeps);
-    else if (I.dtype == kFP8)
-      batch_dispatch_lanes<kFP8>(I, sh, stats, tol, max_sweeps);
+// Member `rank` of a team of I.team workgroups.  Every member runs the same
+// sequence of barriers (the stop decision is taken on the same values by
+// all), so no member waits for a barrier that another skips.
+template <int VT, int LANES>
+__device__ void batch_solve_team(const BatchItem& I, int rank, BatchShared& sh,
+                                 const BatchArgs& A) {
+  constexpr int GPW = kWave / LANES;
+  const int K = I.team;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sl = lane % LANES;
+  const int groups = (blockDim.x >> 6) * GPW;
+  const int gid = rank * groups + wave * GPW + lane / LANES;  // lane group within the team
+  const int gstride = K * groups;
+  const int64_t n = I.n, b = I.b, nb = (n + b - 1) / b;
+  unsigned long long* arrive = &A.ctl->arrive[I.slot];
+  double* dvm = A.team_dv + (size_t)I.slot * 2 * kBatchMaxTeam;  // [2][kBatchMaxTeam]
+  MBDP_GLOBAL double* gnew = gview_mut<double>(A.team_new + (size_t)I.slot * 2 * kBatchMaxB);
+  const MBDP_GLOBAL double* V0 = gview<double>(I.V);
+  for (int64_t j = threadIdx.x; j < I.ld; j += blockDim.x) sh.V[j] = j < n ? V0[j] : 0.0;
+  __syncthreads();
+  long long sweeps = 0;
+  double dv = INFINITY;
+  int converged = 0;
+  unsigned long long phase = 0;
+  bool ok = true;
+  for (uint64_t t = 0; ok && (long long)t < A.max_sweeps; ++t) {
+    const OrderKey key = make_order_key(n, I.seed, t);
+    double dvl = 0.0;
+    for (int64_t k = 0; k < nb; ++k) {
+      const int64_t kb = k * b, bk = min(b, n - kb);
+      MBDP_GLOBAL double* buf = gnew + (phase & 1) * kBatchMaxB;
+      for (int64_t i = gid; i < bk; i += gstride) {
+        const int32_t s = (int32_t)sweep_order_at((uint32_t)(kb + i), key);
+        double q;
+        int a;
+        batch_state<VT, LANES>(I, sh.V, s, sl, q, a);
+        if (sl == 0) {
+          buf[i] = q;
+          dvl = fmax(dvl, fabs(q - sh.V[s]));
+        }
+      }
+      if (k == nb - 1) {  // this member's max |dV| of the sweep, by sweep parity
+        dvl = wave_max_d(dvl);
+        if (lane == 0) sh.red[wave] = dvl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          double d = 0.0;
+          for (int w = 0; w < (int)(blockDim.x >> 6); ++w) d = fmax(d, sh.red[w]);
+          gview_mut<double>(dvm)[(t & 1) * kBatchMaxTeam + rank] = d;
+        }
+      }
+      // buffers of parity p are rewritten at phase p + 2, after barrier p + 1,
+      // which every member reaches only once it has read them
+      ok = team_sync(arrive, &A.ctl->abort, (phase + 1) * (unsigned long long)K,
+                     A.timeout_ticks, sh);
+      if (!ok) break;
+      for (int64_t i = threadIdx.x; i < bk; i += blockDim.x)
+        sh.V[sweep_order_at((uint32_t)(kb + i), key)] = buf[i];
+      ++phase;
+      __syncthreads();  // committed before the next batch reads
+    }
+    if (!ok) break;
+    ++sweeps;
+    dv = 0.0;
+    for (int r = 0; r < K; ++r) dv = fmax(dv, gview<double>(dvm)[(t & 1) * kBatchMaxTeam + r]);
+    if (dv <= A.tol) {
+      converged = 1;
+      break;
+    }
+  }
+  if (ok) {
+    if (rank == 0) {
+      MBDP_GLOBAL double* Vout = gview_mut<double>(I.V);
+      for (int64_t j = threadIdx.x; j < n; j += blockDim.x) Vout[j] = sh.V[j];
+    }
+    if (I.policy) {
+      MBDP_GLOBAL int32_t* pol = gview_mut<int32_t>(I.policy);
+      for (int64_t s = gid; s < n; s += gstride) {
+        double q;
+        int a;
+        batch_state<VT, LANES>(I, sh.V, (int32_t)s, sl, q, a);
+        if (sl == 0) pol[s] = a;
+      }
+    }
+  }
+  if (rank == 0 && threadIdx.x == 0) {
+    BatchStat st;
+    st.sweeps = sweeps;
+    st.dv = dv;
+    st.converged = ok ? converged : 0;
+    st.pad = ok ? 0 : 1;
+    A.stats[I.index] = st;
+  }
+  __syncthreads();
+}
+
+template <int VT>
+__device__ __forceinline__ void batch_dispatch_lanes(const BatchItem& I, int rank,
+                                                     BatchShared& sh, const BatchArgs& A) {
+  if (I.team > 1) {
+    if (I.lanes == 16)
+      batch_solve_team<VT, 16>(I, rank, sh, A);
+    else if (I.lanes == 32)
+      batch_solve_team<VT, 32>(I, rank, sh, A);
     else
-      batch_dispatch_lanes<kF32>(I, sh, stats, tol, max_sweeps);
+      batch_solve_team<VT, 64>(I, rank, sh, A);
+  } else if (I.lanes == 16) {
+    batch_solve_item<VT, 16>(I, sh, A.stats, A.tol, A.max_sweeps);
+  } else if (I.lanes == 32) {
+    batch_solve_item<VT, 32>(I, sh, A.stats, A.tol, A.max_sweeps);
+  } else {
+    batch_solve_item<VT, 64>(I, sh, A.stats, A.tol, A.max_sweeps);
   }
 }
 
-int launch_batch(const BatchItem* items, int count, unsigned* queue, BatchStat* stats, double tol,
-                 long long max_sweeps, int blocks, void* stream) {
+// Tickets 0, 1, ... are handed out in order; item i owns the tickets
+// [ticket0, ticket0 + team), the items ordered by ticket0.
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)))
+batch_kernel(BatchArgs A) {
+  __shared__ BatchShared sh;
+  const BatchItem& last = A.items[A.count - 1];
+  const long long tickets = last.ticket0 + last.team;
+  while (true) {
+    if (threadIdx.x == 0) {
+      const long long u = (long long)atomicAdd(&A.ctl->queue, 1u);
+      int it = A.count;
+      if (u < tickets) {  // the last item whose first ticket is <= u
+        int lo = 0, hi = A.count - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (A.items[mid].ticket0 <= u) lo = mid; else hi = mid - 1;
+        }
+        it = lo;
+        sh.rank = (int)(u - A.items[lo].ticket0);
+      }
+      sh.item = it;
+    }
+    __syncthreads();
+    const int it = sh.item, rank = sh.rank;
+    __syncthreads();
+    if (it >= A.count) break;
+    const BatchItem I = A.items[it];
+    if (I.dtype == kBF16)
+      batch_dispatch_lanes<kBF16>(I, rank, sh, A);
+    else if (I.dtype == kFP8)
+      batch_dispatch_lanes<kFP8>(I, rank, sh, A);
+    else
+      batch_dispatch_lanes<kF32>(I, rank, sh, A);
+    if (__hip_atomic_load(&A.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+  }
+}
+
+int launch_batch(const BatchArgs& a, int blocks, void* stream) {
   hipLaunchKernelGGL(batch_kernel, dim3(blocks), dim3(1024), 0,
-                     reinterpret_cast<hipStream_t>(stream), items, count, queue, stats, tol,
-                     max_sweeps);
+                     reinterpret_cast<hipStream_t>(stream), a);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -173,10 +173,13 @@ int launch_value_gradients(const KParams& p, const int32_t* policy, const double
                            void* stream);
 
 // Many small dense MDPs solved in one launch (mbdp_batch.hip): a workgroup
-// per MDP, V in LDS, FP64 arithmetic.
+// (or a team of up to kBatchMaxTeam workgroups) per MDP, V in LDS, FP64
+// arithmetic.
 constexpr int64_t kBatchMaxN = 8192;  // states (and row stride) per MDP
 constexpr int64_t kBatchMaxB = 4096;  // batch size per MDP
 constexpr int32_t kBatchMaxM = 64;    // actions per MDP
+constexpr int32_t kBatchMaxTeam = 16; // workgroups per MDP
+constexpr int32_t kBatchTeamSlots = 256;  // MDPs served by a team at once
 
 struct BatchItem {
   int64_t n, ld, b;
@@ -190,6 +193,9 @@ struct BatchItem {
   int32_t* policy;
   int32_t lanes;   // lanes per state: 16, 32 or 64
   int32_t index;   // position in the caller's list (results go there)
+  int32_t team;    // workgroups serving the MDP
+  int32_t slot;    // team slot (teams only)
+  int64_t ticket0; // first queue ticket of the MDP; tickets [ticket0, ticket0 + team)
 };
 
 struct BatchStat {
@@ -199,23 +205,52 @@ struct BatchStat {
   int pad;
 };
 
-// Workspace of a batched solve: queue counter (cleared per launch), the
-// item table, the statistics.
+// Control words of a batched launch (cleared per launch): the ticket
+// counter, the abort flag raised by a team barrier that timed out, and one
+// barrier arrival counter per team slot.
+struct BatchControl {
+  unsigned queue;
+  unsigned abort;
+  unsigned pad[14];
+  unsigned long long arrive[kBatchTeamSlots];
+};
+
+inline int32_t batch_team_slots(int32_t count) {
+  return count < kBatchTeamSlots ? count : kBatchTeamSlots;
+}
+
+// Workspace of a batched solve: control words, the item table, the
+// statistics, and per team slot the members' sweep maxima [2][kBatchMaxTeam]
+// and the new values of a batch [2][kBatchMaxB] (both by parity).
 struct BatchLayout {
-  size_t queue, items, stats, total;
+  size_t control, items, stats, team_dv, team_new, total;
 };
 inline BatchLayout batch_layout(int32_t count) {
   BatchLayout l{};
+  const size_t slots = (size_t)batch_team_slots(count);
   size_t off = 0;
-  l.queue = off;  off = align_up(off + 256, 256);
-  l.items = off;  off = align_up(off + (size_t)count * sizeof(BatchItem), 256);
-  l.stats = off;  off = align_up(off + (size_t)count * sizeof(BatchStat), 256);
+  l.control = off;  off = align_up(off + sizeof(BatchControl), 256);
+  l.items = off;    off = align_up(off + (size_t)count * sizeof(BatchItem), 256);
+  l.stats = off;    off = align_up(off + (size_t)count * sizeof(BatchStat), 256);
+  l.team_dv = off;  off = align_up(off + slots * 2 * kBatchMaxTeam * sizeof(double), 256);
+  l.team_new = off; off = align_up(off + slots * 2 * (size_t)kBatchMaxB * sizeof(double), 256);
   l.total = off;
   return l;
 }
 
-int launch_batch(const BatchItem* items, int count, unsigned* queue, BatchStat* stats, double tol,
-                 long long max_sweeps, int blocks, void* stream);
+struct BatchArgs {
+  const BatchItem* items;
+  int count;
+  BatchControl* ctl;
+  BatchStat* stats;
+  double* team_dv;
+  double* team_new;
+  double tol;
+  long long max_sweeps;
+  unsigned long long timeout_ticks;  // a team barrier gives up after this many wall-clock ticks
+};
+
+int launch_batch(const BatchArgs& a, int blocks, void* stream);
 
 // BF16 / FP8 instantiations (mbdp_kernels_lp_*.hip): null when the shape has
 // none (ELL rows of more than 64 entries).

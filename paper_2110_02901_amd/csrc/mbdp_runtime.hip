@@ -68,6 +68,8 @@ mbdp_status fail(mbdp_status st, const char* fmt, ...) {
 constexpr int64_t kMaxStates = (int64_t)1 << 31;  // state indices are int32
 constexpr int32_t kMaxDenseActions = 1024;        // LDS holds one Q per action
 constexpr double kBarrierTimeoutSeconds = 30.0;
+// A team member waits for the others' batch: seconds at most for these sizes.
+constexpr double kBatchTeamTimeoutSeconds = 60.0;
 
 bool gamma_ok(double g) { return isfinite(g) && g > 0.0 && g < 1.0; }
 
@@ -497,6 +499,9 @@ mbdp_status mdp_batch_upload(const mbdp_batch_item* items, int32_t count, void* 
       return fail(MBDP_ERR_INVALID_ARG, "item %d: P must be 16-byte aligned", i);
     if (it.lanes != 0 && it.lanes != 16 && it.lanes != 32 && it.lanes != 64)
       return fail(MBDP_ERR_INVALID_ARG, "item %d: lanes must be 0, 16, 32 or 64", i);
+    if (it.team < 0 || it.team > kBatchMaxTeam)
+      return fail(MBDP_ERR_INVALID_ARG, "item %d: team = %d not in [0, %d]", i, it.team,
+                  kBatchMaxTeam);
     BatchItem& b = table[(size_t)i];
     b.n = it.n;
     b.ld = it.ld;
@@ -514,17 +519,80 @@ mbdp_status mdp_batch_upload(const mbdp_batch_item* items, int32_t count, void* 
     const int epl = it.dtype == MBDP_F32 ? 4 : (it.dtype == MBDP_BF16 ? 8 : 16);
     b.lanes = it.lanes ? it.lanes : (it.ld >= 64 * epl ? 64 : (it.ld >= 32 * epl ? 32 : 16));
     b.index = i;
+    b.team = it.team;
+    b.slot = -1;
+    b.ticket0 = 0;
     // work estimate: bytes per sweep times sweeps to shrink the error 1e6-fold
     const double bytes = (double)it.n * it.m * it.ld * (it.dtype == MBDP_F32 ? 4 : it.dtype == MBDP_BF16 ? 2 : 1);
     work[(size_t)i] = bytes * (13.8 / -log(it.gamma));
   }
-  // largest first, so the long solves start early and small ones fill in
+  // Team sizes.  An MDP whose work exceeds the device's fair share (total
+  // work / compute units) gets that many workgroups, at most kBatchMaxTeam
+  // and at most one per lane-group-width of its batch; all members of all
+  // teams must fit on the device at once (one workgroup per compute unit).
+  int device = 0, cus = 0;
+  MBDP_HIP(hipGetDevice(&device));
+  MBDP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+  double total = 0.0;
+  for (double w : work) total += w;
+  const double share = total / (double)(cus > 0 ? cus : 1);
+  std::vector<int32_t> by_work((size_t)count);
+  for (int32_t i = 0; i < count; ++i) by_work[(size_t)i] = i;
+  std::stable_sort(by_work.begin(), by_work.end(),
+                   [&](int32_t x, int32_t y) { return work[(size_t)x] > work[(size_t)y]; });
+  const int32_t slots = batch_team_slots(count);
+  int64_t members = 0;
+  int32_t teams = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    BatchItem& b = table[(size_t)i];
+    if (b.team != 0 || cus < 2 * kBatchMaxTeam) continue;
+    const int64_t groups = 1024 / b.lanes;
+    int64_t k = (int64_t)ceil(work[(size_t)i] / share);
+    const int64_t kcap = std::min<int64_t>(kBatchMaxTeam, std::max<int64_t>(1, b.b / groups));
+    b.team = (int32_t)std::max<int64_t>(1, std::min(k, kcap));
+  }
+  for (int32_t i = 0; i < count; ++i) {
+    BatchItem& b = table[(size_t)i];
+    if (b.team == 0) b.team = 1;
+    if (b.team > 1) {
+      members += b.team;
+      ++teams;
+    }
+  }
+  // too many: the lightest automatic teams fall back to one workgroup
+  for (int32_t j = count - 1; j >= 0 && (members > cus || teams > slots); --j) {
+    const int32_t i = by_work[(size_t)j];
+    BatchItem& b = table[(size_t)i];
+    if (b.team > 1 && items[i].team == 0) {
+      members -= b.team;
+      --teams;
+      b.team = 1;
+    }
+  }
+  if (members > cus || teams > slots)
+    return fail(MBDP_ERR_UNSUPPORTED,
+                "teams need %lld workgroups in %d teams; the device runs %d at once and a "
+                "launch serves %d teams", (long long)members, teams, cus, slots);
+  // queue order: the teams first (all their members start at once), then the
+  // single workgroups, each part heaviest per workgroup first
   std::vector<int32_t> order((size_t)count);
   for (int32_t i = 0; i < count; ++i) order[(size_t)i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t x, int32_t y) { return work[(size_t)x] > work[(size_t)y]; });
+  auto per_member = [&](int32_t i) { return work[(size_t)i] / table[(size_t)i].team; };
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    const bool tx = table[(size_t)x].team > 1, ty = table[(size_t)y].team > 1;
+    if (tx != ty) return tx;
+    return per_member(x) > per_member(y);
+  });
   std::vector<BatchItem> sorted((size_t)count);
-  for (int32_t i = 0; i < count; ++i) sorted[(size_t)i] = table[(size_t)order[(size_t)i]];
+  int64_t ticket = 0;
+  int32_t slot = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    BatchItem b = table[(size_t)order[(size_t)i]];
+    b.ticket0 = ticket;
+    ticket += b.team;
+    if (b.team > 1) b.slot = slot++;
+    sorted[(size_t)i] = b;
+  }
   char* base = static_cast<char*>(workspace);
   MBDP_HIP(hipMemcpyAsync(base + L.items, sorted.data(), sorted.size() * sizeof(BatchItem),
                           hipMemcpyHostToDevice, stream));
@@ -540,18 +608,30 @@ mbdp_status mdp_batch_launch(int32_t count, double tol_dv, int64_t max_sweeps, v
   if (!workspace || ((uintptr_t)workspace) % 256 || ws_bytes < L.total)
     return fail(MBDP_ERR_WORKSPACE, "batch workspace must be 256-byte aligned with %zu bytes",
                 L.total);
-  int device = 0, cus = 0;
+  int device = 0, cus = 0, khz = 0;
   MBDP_HIP(hipGetDevice(&device));
   MBDP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+  MBDP_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device));
   char* base = static_cast<char*>(workspace);
-  // kernels only (a fill kernel clears the queue), so the call can be captured
-  if (launch_zero(base + L.queue, 256, stream) != 0)
+  // kernels only (a fill kernel clears the control words), so the call can be captured
+  if (launch_zero(base + L.control, sizeof(BatchControl), stream) != 0)
     return fail(MBDP_ERR_HIP, "clear failed: %s", hipGetErrorString(hipGetLastError()));
-  const int blocks = cus < count ? cus : count;
-  if (launch_batch(reinterpret_cast<const BatchItem*>(base + L.items), count,
-                   reinterpret_cast<unsigned*>(base + L.queue),
-                   reinterpret_cast<BatchStat*>(base + L.stats), tol_dv, (long long)max_sweeps,
-                   blocks, stream) != 0)
+  BatchArgs a{};
+  a.items = reinterpret_cast<const BatchItem*>(base + L.items);
+  a.count = count;
+  a.ctl = reinterpret_cast<BatchControl*>(base + L.control);
+  a.stats = reinterpret_cast<BatchStat*>(base + L.stats);
+  a.team_dv = reinterpret_cast<double*>(base + L.team_dv);
+  a.team_new = reinterpret_cast<double*>(base + L.team_new);
+  a.tol = tol_dv;
+  a.max_sweeps = (long long)max_sweeps;
+  a.timeout_ticks = (unsigned long long)(kBatchTeamTimeoutSeconds * 1000.0 *
+                                         (double)(khz > 0 ? khz : 100000));
+  // one workgroup per compute unit at most (the LDS holds one), and at least
+  // every member of every team, which the upload kept within the device
+  const int64_t want = (int64_t)count * kBatchMaxTeam;
+  const int blocks = (int)std::min<int64_t>(cus, want);
+  if (launch_batch(a, blocks, stream) != 0)
     return fail(MBDP_ERR_HIP, "batch launch failed: %s", hipGetErrorString(hipGetLastError()));
   return MBDP_OK;
 }
@@ -561,9 +641,14 @@ mbdp_status mdp_batch_read_stats(void* workspace, int32_t count, mbdp_batch_stat
   if (count < 1 || !workspace || !out) return fail(MBDP_ERR_INVALID_ARG, "bad arguments");
   const BatchLayout L = batch_layout(count);
   std::vector<BatchStat> st((size_t)count);
+  BatchControl ctl{};
   MBDP_HIP(hipMemcpyAsync(st.data(), static_cast<char*>(workspace) + L.stats,
                           st.size() * sizeof(BatchStat), hipMemcpyDeviceToHost, stream));
+  MBDP_HIP(hipMemcpyAsync(&ctl, static_cast<char*>(workspace) + L.control, sizeof ctl,
+                          hipMemcpyDeviceToHost, stream));
   MBDP_HIP(hipStreamSynchronize(stream));
+  if (ctl.abort)
+    return fail(MBDP_ERR_DEVICE, "a team barrier of the batched launch timed out");
   for (int32_t i = 0; i < count; ++i) {
     out[i].sweeps = st[(size_t)i].sweeps;
     out[i].final_dv_inf = st[(size_t)i].dv;

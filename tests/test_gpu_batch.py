@@ -151,3 +151,51 @@ def test_batch_at_scale_sampled():
         err = float(np.max(np.abs(item["V"].cpu().numpy() - ref)))
         say("item %d n=%d: max err %.3g" % (i, item["n"], err))
         assert err <= 1e-11 * max(1.0, float(np.max(np.abs(ref))))
+
+
+def test_batch_teams_match_single_workgroups():
+    """A team of workgroups on one MDP computes the same iterates as one
+    workgroup (the same arithmetic per state), for team sizes with members
+    idle in some batches (b below the team's lane groups) and sizes that
+    split every batch; both after a fixed number of sweeps and with the
+    stop rule (the same sweep count)."""
+    specs = [(700, 8, "bf16", 0.9, 88, 16), (1000, 4, "fp8", 0.95, 125, 64),
+             (333, 2, "f32", 0.93, 42, 32), (2048, 8, "bf16", 0.97, 256, 16),
+             (50, 3, "f32", 0.8, 7, 16)]
+    for T, tol in ((9, -1.0), (100000, 1e-9)):
+        base = [make_item(n, m, dt, g, b, 700 + i, 60 + i, lanes, with_oracle=False)
+                for i, (n, m, dt, g, b, lanes) in enumerate(specs)]
+        runs = {}
+        for teams in ((1, 1, 1, 1, 1), (2, 3, 5, 16, 2), (16, 2, 3, 4, 7)):
+            items = []
+            for (it, _, V0), k in zip(base, teams):
+                it = dict(it)
+                it["V"] = up(V0.copy())
+                it["policy"] = torch.zeros(it["n"], dtype=torch.int32, device=dev())
+                it["team"] = k
+                items.append(it)
+            ws = mb.batch_workspace(len(items))
+            mb.mdp_batch_upload(items, ws)
+            mb.mdp_batch_launch(len(items), tol, T, ws)
+            stats = mb.mdp_batch_read_stats(ws, len(items))
+            runs[teams] = ([it["V"].cpu() for it in items], [it["policy"].cpu() for it in items],
+                           [(st["sweeps"], st["converged"]) for st in stats])
+            say("T=%d tol=%g teams %s: sweeps %s" % (T, tol, teams, [s[0] for s in runs[teams][2]]))
+        ref = runs[(1, 1, 1, 1, 1)]
+        for teams, (Vs, pols, sts) in runs.items():
+            assert sts == ref[2], teams
+            for i in range(len(specs)):
+                assert torch.equal(Vs[i], ref[0][i]), (teams, i)
+                assert torch.equal(pols[i], ref[1][i]), (teams, i)
+        if tol > 0:
+            assert all(c for _, c in ref[2])
+
+
+def test_batch_rejects_bad_team_sizes():
+    item, _, _ = make_item(64, 2, "f32", 0.9, 8, 1, 2, with_oracle=False)
+    ws = mb.batch_workspace(1)
+    for bad in (-1, 17):
+        it = dict(item)
+        it["team"] = bad
+        with pytest.raises(RuntimeError):
+            mb.mdp_batch_upload([it], ws)
