@@ -174,6 +174,18 @@ def run_batch(args, dev):
     sweeps = [st["sweeps"] for st in stats]
     log("batch: %d MDPs, sweeps %d..%d (mean %.0f), %.1f ms per solve of all"
         % (count, min(sweeps), max(sweeps), float(np.mean(sweeps)), kernel_s / args.steps * 1e3))
+    # schedule of the last launch: how long the compute units were busy
+    span = max(st["end_us"] for st in stats)
+    busy = sum((st["end_us"] - st["start_us"]) * st["team"] for st in stats)
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    teams = [st["team"] for st in stats if st["team"] > 1]
+    log("schedule: span %.1f ms, compute units busy %.0f%%, %d teams (%d workgroups)"
+        % (span / 1e3, 100.0 * busy / (cus * span), len(teams), sum(teams)))
+    for i in sorted(range(count), key=lambda i: -stats[i]["end_us"])[:6]:
+        st = stats[i]
+        log("  n=%d gamma=%.3f team=%d sweeps=%d: %.1f .. %.1f ms"
+            % (ns[i], gammas[i], st["team"], st["sweeps"], st["start_us"] / 1e3,
+               st["end_us"] / 1e3))
     line = {
         "metric": METRIC, "value": backups * args.steps / wall, "unit": "backups/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -185,6 +197,8 @@ def run_batch(args, dev):
                    "storage": "bf16", "tol_dv": tol, "launch": "hipGraph replay"},
         "hbm_gbps": gbps,
         "sweeps": {"min": min(sweeps), "max": max(sweeps), "mean": float(np.mean(sweeps))},
+        "schedule": {"span_ms": span / 1e3, "cu_busy": busy / (cus * span),
+                     "teams": len(teams), "team_workgroups": sum(teams)},
         "lanes": None if tuned is None else {"%s/%d" % k: v[0] for k, v in tuned.items()},
         "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": gbps / HBM_PEAK_GBPS, "traffic": None,

@@ -209,7 +209,9 @@ typedef struct {
   int64_t sweeps;
   double final_dv_inf;    /* max |dV| of the last sweep */
   int32_t converged;      /* final_dv_inf <= tol_dv */
-  int32_t reserved;
+  int32_t team;           /* workgroups that served the MDP */
+  double start_us;        /* when its solve started and ended, in microseconds */
+  double end_us;          /* after the earliest start of the launch (device clock) */
 } mbdp_batch_stats;
 
 /* Workspace bytes of a batch of `count` MDPs (0 if count < 1). */

@@ -86,7 +86,8 @@ class BatchItem(ctypes.Structure):
 
 class BatchStats(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int64), ("final_dv_inf", ctypes.c_double),
-                ("converged", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("converged", ctypes.c_int32), ("team", ctypes.c_int32),
+                ("start_us", ctypes.c_double), ("end_us", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -344,8 +345,8 @@ def mdp_batch_launch(count, tol_dv, max_sweeps, ws, stream=None):
 def mdp_batch_read_stats(ws, count, stream=None):
     out = (BatchStats * count)()
     _check(lib().mdp_batch_read_stats(_ptr(ws), int(count), out, _stream(stream)))
-    return [{"sweeps": o.sweeps, "final_dv_inf": o.final_dv_inf, "converged": o.converged}
-            for o in out]
+    return [{"sweeps": o.sweeps, "final_dv_inf": o.final_dv_inf, "converged": o.converged,
+             "team": o.team, "start_us": o.start_us, "end_us": o.end_us} for o in out]
 
 
 def mdp_destroy(h):

@@ -169,6 +169,7 @@ __device__ void batch_solve_item(const BatchItem& I, BatchShared& sh, BatchStat*
   const MBDP_GLOBAL double* V0 = gview<double>(I.V);
   for (int64_t j = threadIdx.x; j < I.ld; j += blockDim.x) sh.V[j] = j < n ? V0[j] : 0.0;
   __syncthreads();
+  const unsigned long long t_start = wall_clock64();
   long long sweeps = 0;
   double dv = INFINITY;
   int converged = 0;
@@ -222,6 +223,8 @@ __device__ void batch_solve_item(const BatchItem& I, BatchShared& sh, BatchStat*
     st.dv = dv;
     st.converged = converged;
     st.pad = 0;
+    st.t_start = t_start;
+    st.t_end = wall_clock64();
     stats[I.index] = st;
   }
   __syncthreads();
@@ -283,6 +286,7 @@ __device__ void batch_solve_team(const BatchItem& I, int rank, BatchShared& sh,
   const MBDP_GLOBAL double* V0 = gview<double>(I.V);
   for (int64_t j = threadIdx.x; j < I.ld; j += blockDim.x) sh.V[j] = j < n ? V0[j] : 0.0;
   __syncthreads();
+  const unsigned long long t_start = wall_clock64();
   long long sweeps = 0;
   double dv = INFINITY;
   int converged = 0;
@@ -354,6 +358,8 @@ __device__ void batch_solve_team(const BatchItem& I, int rank, BatchShared& sh,
     st.dv = dv;
     st.converged = ok ? converged : 0;
     st.pad = ok ? 0 : 1;
+    st.t_start = t_start;  // member 0's: the team starts together
+    st.t_end = wall_clock64();
     A.stats[I.index] = st;
   }
   __syncthreads();

@@ -203,6 +203,7 @@ struct BatchStat {
   double dv;
   int converged;
   int pad;
+  unsigned long long t_start, t_end;  // device wall clock when the solve started / ended
 };
 
 // Control words of a batched launch (cleared per launch): the ticket

@@ -649,12 +649,26 @@ mbdp_status mdp_batch_read_stats(void* workspace, int32_t count, mbdp_batch_stat
   MBDP_HIP(hipStreamSynchronize(stream));
   if (ctl.abort)
     return fail(MBDP_ERR_DEVICE, "a team barrier of the batched launch timed out");
+  std::vector<BatchItem> table((size_t)count);
+  MBDP_HIP(hipMemcpyAsync(table.data(), static_cast<char*>(workspace) + L.items,
+                          table.size() * sizeof(BatchItem), hipMemcpyDeviceToHost, stream));
+  int device = 0, khz = 0;
+  MBDP_HIP(hipGetDevice(&device));
+  MBDP_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device));
+  MBDP_HIP(hipStreamSynchronize(stream));
+  const double us_per_tick = 1000.0 / (double)(khz > 0 ? khz : 100000);
+  unsigned long long t0 = ~0ull;
+  for (const BatchStat& s : st) t0 = std::min(t0, s.t_start);
   for (int32_t i = 0; i < count; ++i) {
     out[i].sweeps = st[(size_t)i].sweeps;
     out[i].final_dv_inf = st[(size_t)i].dv;
     out[i].converged = st[(size_t)i].converged;
-    out[i].reserved = 0;
+    out[i].team = 0;
+    out[i].start_us = (double)(st[(size_t)i].t_start - t0) * us_per_tick;
+    out[i].end_us = (double)(st[(size_t)i].t_end - t0) * us_per_tick;
   }
+  for (const BatchItem& b : table)
+    if (b.index >= 0 && b.index < count) out[b.index].team = b.team;
   return MBDP_OK;
 }
 

@@ -178,6 +178,8 @@ def test_batch_teams_match_single_workgroups():
             mb.mdp_batch_upload(items, ws)
             mb.mdp_batch_launch(len(items), tol, T, ws)
             stats = mb.mdp_batch_read_stats(ws, len(items))
+            assert [st["team"] for st in stats] == list(teams)
+            assert all(0.0 <= st["start_us"] <= st["end_us"] for st in stats)
             runs[teams] = ([it["V"].cpu() for it in items], [it["policy"].cpu() for it in items],
                            [(st["sweeps"], st["converged"]) for st in stats])
             say("T=%d tol=%g teams %s: sweeps %s" % (T, tol, teams, [s[0] for s in runs[teams][2]]))
