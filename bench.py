@@ -34,28 +34,43 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def library_hash():
+# Sources of each profiled kernel: a committed counter summary is used only
+# while these files are unchanged.
+_BATCH_ONLY = ("mbdp_batch.hip",)
+_SOLVE_ONLY = ("mbdp_kernels.hip", "mbdp_kernels_lp_dense.hip", "mbdp_kernels_lp_ell.hip",
+               "mbdp_kernels_lp_band.hip")
+
+
+def sources_hash(kernel="solve"):
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2110_02901_amd", "csrc")
+    skip = _BATCH_ONLY if kernel == "solve" else _SOLVE_ONLY
     for f in sorted(os.listdir(csrc)):
+        if f in skip:
+            continue
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def _traffic_file(workload):
+    path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % workload)
+    if not os.path.exists(path):
+        return {}
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    return vals
 
 
 def committed_traffic(workload, b, sweeps_per_launch):
     """HBM bytes per launch from the committed rocprofv3 counter summary
     (sweeps x bytes per sweep + the one-off prologue), if the counters were
     taken with the current kernel sources at this batch size; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % workload)
-    if not os.path.exists(path):
-        return None
-    vals = {}
-    for line in open(path):
-        if "=" in line and not line.startswith("#"):
-            k, v = line.split("=", 1)
-            vals[k.strip()] = v.strip()
-    if vals.get("library_hash") != library_hash() or vals.get("b") != str(b):
+    vals = _traffic_file(workload)
+    if vals.get("sources_hash") != sources_hash("solve") or vals.get("b") != str(b):
         return None
     try:
         per_sweep = float(vals["hbm_bytes_per_sweep"])
@@ -136,6 +151,23 @@ def run_batch(args, dev):
             {"%s/%d" % k: v[0] for k, v in tuned.items()}))
     ws = mb.batch_workspace(count)
     mb.mdp_batch_upload(items, ws)
+    if args.profile_sweeps:
+        # counter runs: two eager launches of exactly S and 3S sweeps of every MDP
+        out = {"workload": "batch-512", "launches": [], "sources_hash": sources_hash("batch"),
+               "algorithmic_bytes_per_sweep": float(total_bytes)}
+        for sweeps in (args.profile_sweeps, 3 * args.profile_sweeps):
+            for it in items:
+                it["V"].zero_()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            mb.mdp_batch_launch(count, -1.0, sweeps, ws)
+            e1.record()
+            e1.synchronize()
+            out["launches"].append({"sweeps": sweeps, "ms": e0.elapsed_time(e1)})
+        print(json.dumps(out), flush=True)
+        return
     stream = torch.cuda.Stream()
     graph = torch.cuda.CUDAGraph()
     stream.wait_stream(torch.cuda.current_stream())
@@ -171,6 +203,14 @@ def run_batch(args, dev):
     bytes_step = sum(st["sweeps"] * int(ns[i]) * m * (2 * items[i]["ld"] + 8)
                      for i, st in enumerate(stats))
     gbps = bytes_step * args.steps / kernel_s / 1e9
+    traffic = None
+    vals = _traffic_file("batch-512")
+    if vals.get("sources_hash") == sources_hash("batch"):
+        try:
+            traffic = (float(vals["hbm_bytes_per_sweep"]) / float(vals["algorithmic_bytes_per_sweep"])
+                       * bytes_step + float(vals["hbm_bytes_prologue"]))
+        except (KeyError, ValueError):
+            traffic = None
     sweeps = [st["sweeps"] for st in stats]
     log("batch: %d MDPs, sweeps %d..%d (mean %.0f), %.1f ms per solve of all"
         % (count, min(sweeps), max(sweeps), float(np.mean(sweeps)), kernel_s / args.steps * 1e3))
@@ -191,7 +231,7 @@ def run_batch(args, dev):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
+        "data": "synthetic", "replay_ms": kernel_s / args.steps * 1e3,
         "config": {"workload": "batch-512", "count": count, "n": "U[256, 4096]", "m": m,
                    "alpha": 1.0, "gamma": "U[0.9, 0.99]", "b": "ceil(n / 8)",
                    "storage": "bf16", "tol_dv": tol, "launch": "hipGraph replay"},
@@ -201,8 +241,8 @@ def run_batch(args, dev):
                      "teams": len(teams), "team_workgroups": sum(teams)},
         "lanes": None if tuned is None else {"%s/%d" % k: v[0] for k, v in tuned.items()},
         "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": "batch_kernel (a workgroup per MDP)",
+                     "frac": gbps / HBM_PEAK_GBPS, "traffic": traffic,
+                     "kernel": "batch_kernel (a workgroup or a team per MDP)",
                      "algorithmic_bytes_per_backup": "2 ld + 8"},
     }
     print(json.dumps(line), flush=True)
@@ -308,7 +348,7 @@ def main():
         b = batch_sizes[0]
         out = {"b": b, "engine": mb.mdp_engine(h, b), "launches": [],
                "algorithmic_bytes_per_sweep": n * m * bytes_per_backup,
-               "library_hash": library_hash()}
+               "sources_hash": sources_hash("solve")}
         for sweeps in (args.profile_sweeps, 3 * args.profile_sweeps):
             V = torch.zeros(n, dtype=torch.float32, device=dev)
             e0 = torch.cuda.Event(enable_timing=True)
