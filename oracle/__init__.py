@@ -23,6 +23,9 @@ Lygeros; arXiv 2110.02901):
 * ``adjoint``     -- gradients of L = w^T J* with respect to the costs and the
                      stored transition values at the optimal policy, via the
                      adjoint equation (I - gamma P_mu)^T lambda = w.
+* ``multi``       -- r value vectors (one per cost vector) backed up against
+                     one P with a shared order: MB-VI column by column,
+                     one matrix product per batch.
 * ``quantize``    -- BF16 / FP8 E4M3 storage of transition rows with one
                      scale per row renormalising it to sum 1 (the reduced-
                      precision variant; the paper fixes no precision).

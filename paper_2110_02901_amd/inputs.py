@@ -168,6 +168,12 @@ def inadmissible(c, frac, seed):
     return c
 
 
+def multi_costs(n, m, r, seed, low=0.0, high=1.0, dtype=np.float32):
+    """r cost vectors at once, C[s, a, j] ~ U[low, high), layout [n, m, r]."""
+    g = _rng(seed, _STREAM_MISC, 3)
+    return (low + (high - low) * g.random((n, m, r))).astype(dtype)
+
+
 def values(n, seed, low=0.0, high=1.0, dtype=np.float32):
     """A random value vector V ~ U[low, high)."""
     g = _rng(seed, _STREAM_MISC, 2)
