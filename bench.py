@@ -34,20 +34,20 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-# Sources of each profiled kernel: a committed counter summary is used only
-# while these files are unchanged.
-_BATCH_ONLY = ("mbdp_batch.hip",)
-_SOLVE_ONLY = ("mbdp_kernels.hip", "mbdp_kernels_lp_dense.hip", "mbdp_kernels_lp_ell.hip",
-               "mbdp_kernels_lp_band.hip")
+# Device sources of each profiled kernel: a committed counter summary is
+# used only while these files are unchanged.
+_KERNEL_SOURCES = {
+    "solve": ("mbdp_device.h", "mbdp_engines.h", "mbdp_kernels.hip", "mbdp_kernels_lp_dense.hip",
+              "mbdp_kernels_lp_ell.hip", "mbdp_kernels_lp_band.hip"),
+    "batch": ("mbdp_device.h", "mbdp_engines.h", "mbdp_batch.hip"),
+    "multi": ("mbdp_device.h", "mbdp_multi.hip"),
+}
 
 
 def sources_hash(kernel="solve"):
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2110_02901_amd", "csrc")
-    skip = _BATCH_ONLY if kernel == "solve" else _SOLVE_ONLY
-    for f in sorted(os.listdir(csrc)):
-        if f in skip:
-            continue
+    for f in _KERNEL_SOURCES[kernel]:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -239,6 +239,43 @@ mbdp_status mdp_batch_launch(int32_t count, double tol_dv, int64_t max_sweeps, v
 mbdp_status mdp_batch_read_stats(void* workspace, int32_t count, mbdp_batch_stats* out,
                                  hipStream_t stream);
 
+/* Several value vectors against one P (an extension): r cost vectors
+ * C[:, :, j] share the handle's transition probabilities, gamma, the batch
+ * size b and the sweep orders sigma_t; V[:, j] follows MB-VI (Sec. III-B,
+ * eqs. (10)-(12)) of the MDP with costs C[:, :, j] (the handle's own costs
+ * are not used).  For one batch the expected values of all r vectors are
+ * one matrix product (the batch's rows of P against V), run on the matrix
+ * cores.  V is held as an FP64 anchor plus a small difference that goes
+ * through the products as two BF16 terms; the anchor is refreshed (an FP64
+ * pass over P) whenever the products' error bound would reach a twentieth
+ * of the last sweep's change, so the iterates follow the FP64 ones. */
+typedef struct {
+  int64_t sweeps;        /* sweeps applied */
+  double final_dv_inf;   /* max over vectors and states of |dV| in the last sweep */
+  int64_t recentrings;   /* anchor refreshes after the start */
+  int32_t converged;     /* final_dv_inf <= tol_dv */
+  int32_t reserved;
+} mbdp_multi_stats;
+
+/* Workspace bytes of mdp_multi_solve for this handle, r and b (0 if the
+ * handle is not dense BF16 with n % 32 == 0, r is not 16, 32, 48 or 64, or b
+ * is not in [1, n]). */
+size_t mdp_multi_workspace_bytes(mbdp_mdp_t h, int32_t r, int64_t b);
+
+/* MB-VI on r vectors at once.  C: device FP32 [n][m][r]; V: device FP64
+ * [n][r], V0 in, the last iterate out; policy: device int32 [n][r], the
+ * greedy actions at the last iterate (lowest index on ties), or NULL.  Sweep
+ * t (t = first_sweep, first_sweep + 1, ...) uses sigma_t of `seed`.  Stops
+ * after the first sweep with max |dV| <= tol_dv (over all vectors; tol_dv < 0
+ * disables the rule) or after max_sweeps; MBDP_ERR_NOT_CONVERGED (soft) when
+ * the limit was reached with tol_dv >= 0.  Needs a dense BF16 handle
+ * (mdp_create_dense_q) with n % 32 == 0 and r in {16, 32, 48, 64};
+ * synchronises `stream`. */
+mbdp_status mdp_multi_solve(mbdp_mdp_t h, int32_t r, const float* C, double* V, int32_t* policy,
+                            int64_t b, uint64_t seed, uint64_t first_sweep, double tol_dv,
+                            int64_t max_sweeps, void* workspace, size_t ws_bytes,
+                            hipStream_t stream, mbdp_multi_stats* stats);
+
 /* Replaces the handle's tuning knobs. */
 mbdp_status mdp_set_tuning(mbdp_mdp_t h, const mbdp_tuning* t);
 

@@ -39,7 +39,7 @@ EXPORTS = [
     "mdp_create_dense", "mdp_create_csr", "mdp_create_dense_q", "mdp_create_csr_q",
     "mdp_quantize_rows", "mdp_policy_transpose", "mdp_value_gradients", "mdp_destroy",
     "mdp_set_tuning", "mdp_batch_workspace_bytes", "mdp_batch_upload", "mdp_batch_launch",
-    "mdp_batch_read_stats",
+    "mdp_batch_read_stats", "mdp_multi_workspace_bytes", "mdp_multi_solve",
     "mdp_workspace_bytes", "mdp_engine", "mdp_validate", "mbdp_permutation", "mb_sweep",
     "mbdp_sync_status", "vi_solve", "mpi_solve", "mbdp_last_error",
 ]
@@ -96,6 +96,15 @@ class Tuning(ctypes.Structure):
                 ("band_window", ctypes.c_int32)]
 
 
+class MultiStats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("final_dv_inf", ctypes.c_double),
+                ("recentrings", ctypes.c_int64), ("converged", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _U64 = ctypes.c_uint64
@@ -114,6 +123,9 @@ _SIGS = {
     "mdp_batch_upload": (_I32, [ctypes.POINTER(BatchItem), _I32, _P, ctypes.c_size_t, _P]),
     "mdp_batch_launch": (_I32, [_I32, _D, _I64, _P, ctypes.c_size_t, _P]),
     "mdp_batch_read_stats": (_I32, [_P, _I32, ctypes.POINTER(BatchStats), _P]),
+    "mdp_multi_workspace_bytes": (ctypes.c_size_t, [_P, _I32, _I64]),
+    "mdp_multi_solve": (_I32, [_P, _I32, _P, _P, _P, _I64, _U64, _U64, _D, _I64, _P,
+                               ctypes.c_size_t, _P, ctypes.POINTER(MultiStats)]),
     "mdp_value_gradients": (_I32, [_P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "mdp_set_tuning": (_I32, [_P, ctypes.POINTER(Tuning)]),
     "mdp_workspace_bytes": (ctypes.c_size_t, [_P, _I64]),
@@ -318,6 +330,36 @@ def batch_workspace(count):
     buf = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
     off = (-buf.data_ptr()) % 256
     return buf[off:off + nbytes]
+
+
+def multi_workspace(h, r, b):
+    """A torch uint8 workspace for mdp_multi_solve (256-byte aligned)."""
+    import torch
+    nbytes = int(lib().mdp_multi_workspace_bytes(h.ptr, int(r), int(b)))
+    if nbytes == 0:
+        raise MbdpError(MBDP_ERR_INVALID_ARG, "no multi-vector workspace for this handle, r and b")
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + nbytes]
+
+
+def mdp_multi_solve(h, C, V, b, seed, ws, tol_dv=1e-8, max_sweeps=100000, first_sweep=0,
+                    policy=None, stream=None):
+    """MB-VI on r vectors at once: C FP32 [n, m, r], V FP64 [n, r] (V0 in, result
+    out), policy int32 [n, r] or None.  Returns the statistics as a dict."""
+    import torch
+    r = int(C.shape[2])
+    _require(C, torch.float32, h.n * h.m * r, "C")
+    _require(V, torch.float64, h.n * r, "V")
+    if policy is not None:
+        _require(policy, torch.int32, h.n * r, "policy")
+    st = MultiStats()
+    status = lib().mdp_multi_solve(h.ptr, r, _ptr(C), _ptr(V), _ptr(policy), int(b),
+                                   int(seed), int(first_sweep), float(tol_dv), int(max_sweeps),
+                                   _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(st))
+    if status not in (MBDP_OK, MBDP_ERR_NOT_CONVERGED):
+        _check(status)
+    return st.as_dict()
 
 
 def mdp_batch_upload(items, ws, stream=None):

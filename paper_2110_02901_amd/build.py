@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmbdp.so")
 OBJDIR = os.path.join(HERE, "_build")
 # one translation unit per kernel family, compiled in parallel
-SOURCES = ["mbdp_kernels.hip", "mbdp_kernels_lp_dense.hip", "mbdp_kernels_lp_ell.hip", "mbdp_batch.hip",
+SOURCES = ["mbdp_kernels.hip", "mbdp_kernels_lp_dense.hip", "mbdp_kernels_lp_ell.hip", "mbdp_batch.hip", "mbdp_multi.hip",
            "mbdp_kernels_lp_band.hip", "mbdp_runtime.hip"]
 
 COMPILE_FLAGS = [

@@ -253,6 +253,75 @@ struct BatchArgs {
 
 int launch_batch(const BatchArgs& a, int blocks, void* stream);
 
+// Several value vectors against one dense BF16 P (mbdp_multi.hip).
+constexpr int32_t kMultiMaxR = 64;
+
+struct MultiControl {
+  unsigned long long dv_bits;  // max |dV| of the sweep in progress (bits of a non-negative double)
+  double dv_last;              // max |dV| of the last completed sweep
+  double w_bound;              // sum of the sweeps' max |dV| since the last re-centring (>= max |W|)
+  long long sweeps;            // sweeps completed
+  unsigned done;               // a sweep met the stop rule: the sweep kernels return at once
+  unsigned pad[7];
+};
+
+struct MultiArgs {
+  int64_t n;
+  int32_t m, r;
+  double gamma;
+  int64_t b;
+  uint64_t seed;
+  double tol;
+  const uint16_t* P;     // BF16 codes [n][m][n]
+  const float* rscale;   // [n * m]
+  const float* C;        // [n][m][r]
+  double* R;             // anchor [n][r]
+  double* W;             // V - R [n][r]
+  uint16_t* Ws;          // W as two BF16 terms [2][r][n]
+  double* PR;            // scale * codes . R per row [n * m][r]
+  float* part;           // partial products [splits][part_rows][r]
+  int64_t part_rows;     // b * m
+  int64_t kchunk;        // K per split, a multiple of 32
+  int32_t splits;
+  int32_t* policy;       // [n][r] or null
+  MultiControl* ctl;
+};
+
+// rows of P per wavefront of the product kernel: 16 per 16 vectors
+inline int64_t multi_rows_per_wave(int32_t r) { return r; }
+
+struct MultiLayout {
+  size_t ctl, R, W, Ws, PR, part, total;
+  int64_t kchunk;
+  int32_t splits;
+};
+// Split K so that a batch's product runs on about 2048 wavefronts.
+inline MultiLayout multi_layout(int64_t n, int32_t m, int32_t r, int64_t b) {
+  MultiLayout l{};
+  const int64_t tiles = (b * m + multi_rows_per_wave(r) - 1) / multi_rows_per_wave(r);
+  int64_t splits = (2048 + tiles - 1) / tiles;
+  const int64_t max_splits = n / 256 > 0 ? n / 256 : 1;
+  if (splits > max_splits) splits = max_splits;
+  if (splits < 1) splits = 1;
+  l.kchunk = ((n + splits - 1) / splits + 31) / 32 * 32;
+  l.splits = (int32_t)((n + l.kchunk - 1) / l.kchunk);
+  size_t off = 0;
+  l.ctl = off;  off = align_up(off + sizeof(MultiControl), 256);
+  l.R = off;    off = align_up(off + (size_t)n * r * sizeof(double), 256);
+  l.W = off;    off = align_up(off + (size_t)n * r * sizeof(double), 256);
+  l.Ws = off;   off = align_up(off + 2 * (size_t)r * n * sizeof(uint16_t), 256);
+  l.PR = off;   off = align_up(off + (size_t)n * m * r * sizeof(double), 256);
+  l.part = off; off = align_up(off + (size_t)l.splits * b * m * r * sizeof(float), 256);
+  l.total = off;
+  return l;
+}
+
+int launch_multi_gemm(const MultiArgs& a, uint64_t t, int64_t k, int full, void* stream);
+int launch_multi_commit(const MultiArgs& a, uint64_t t, int64_t k, int mode, void* stream);
+int launch_multi_end(const MultiArgs& a, void* stream);
+int launch_multi_anchor(const MultiArgs& a, double* V, int mode, void* stream);
+int launch_multi_pr(const MultiArgs& a, void* stream);
+
 // BF16 / FP8 instantiations (mbdp_kernels_lp_*.hip): null when the shape has
 // none (ELL rows of more than 64 entries).
 typedef void (*SolveFn)(KParams);

@@ -672,6 +672,123 @@ mbdp_status mdp_batch_read_stats(void* workspace, int32_t count, mbdp_batch_stat
   return MBDP_OK;
 }
 
+namespace {
+
+mbdp_status multi_check(const mbdp_mdp* h, int32_t r, int64_t b) {
+  if (!h) return fail(MBDP_ERR_INVALID_ARG, "handle is NULL");
+  if (h->storage != kDense || h->vdtype != kBF16)
+    return fail(MBDP_ERR_UNSUPPORTED, "multi-vector backups need a dense BF16 handle (mdp_create_dense_q)");
+  if (h->n % 32 != 0)
+    return fail(MBDP_ERR_UNSUPPORTED, "multi-vector backups need n %% 32 == 0 (got n = %lld)",
+                (long long)h->n);
+  if (r != 16 && r != 32 && r != 48 && r != 64)
+    return fail(MBDP_ERR_INVALID_ARG, "r = %d is not 16, 32, 48 or 64", r);
+  if (b < 1 || b > h->n) return fail(MBDP_ERR_INVALID_ARG, "b = %lld not in [1, n]", (long long)b);
+  return MBDP_OK;
+}
+
+// Fold W into the anchor when the products' error bound (2^-16 max|W|)
+// would reach a twentieth of the last sweep's change.
+constexpr double kMultiSplitError = 1.0 / 65536.0;
+constexpr double kMultiErrorShare = 0.05;
+constexpr int kMultiChunk = 8;  // sweeps enqueued between reads of the control block
+
+}  // namespace
+
+size_t mdp_multi_workspace_bytes(mbdp_mdp_t h, int32_t r, int64_t b) {
+  if (multi_check(h, r, b) != MBDP_OK) return 0;
+  return multi_layout(h->n, h->m, r, b).total;
+}
+
+mbdp_status mdp_multi_solve(mbdp_mdp_t h, int32_t r, const float* C, double* V, int32_t* policy,
+                            int64_t b, uint64_t seed, uint64_t first_sweep, double tol_dv,
+                            int64_t max_sweeps, void* workspace, size_t ws_bytes,
+                            hipStream_t stream, mbdp_multi_stats* stats) {
+  mbdp_status st = multi_check(h, r, b);
+  if (st != MBDP_OK) return st;
+  if (!C || !V) return fail(MBDP_ERR_INVALID_ARG, "C or V is NULL");
+  if (max_sweeps < 1) return fail(MBDP_ERR_INVALID_ARG, "max_sweeps must be >= 1");
+  const MultiLayout L = multi_layout(h->n, h->m, r, b);
+  if (!workspace || ((uintptr_t)workspace) % 256 || ws_bytes < L.total)
+    return fail(MBDP_ERR_WORKSPACE, "multi-vector workspace must be 256-byte aligned with %zu bytes",
+                L.total);
+  MBDP_HIP(hipSetDevice(h->device));
+  char* base = static_cast<char*>(workspace);
+  MultiArgs a{};
+  a.n = h->n;
+  a.m = h->m;
+  a.r = r;
+  a.gamma = h->gamma;
+  a.b = b;
+  a.seed = seed;
+  a.tol = tol_dv;
+  a.P = static_cast<const uint16_t*>(h->pq);
+  a.rscale = h->rscale;
+  a.C = C;
+  a.R = reinterpret_cast<double*>(base + L.R);
+  a.W = reinterpret_cast<double*>(base + L.W);
+  a.Ws = reinterpret_cast<uint16_t*>(base + L.Ws);
+  a.PR = reinterpret_cast<double*>(base + L.PR);
+  a.part = reinterpret_cast<float*>(base + L.part);
+  a.part_rows = b * h->m;
+  a.kchunk = L.kchunk;
+  a.splits = L.splits;
+  a.policy = policy;
+  a.ctl = reinterpret_cast<MultiControl*>(base + L.ctl);
+  const char* what = nullptr;
+  auto ok = [&](int rc, const char* name) {
+    if (rc != 0 && !what) what = name;
+    return rc == 0;
+  };
+  // anchor at V0: R = V0, W = 0, PR = P R
+  ok(launch_zero(base + L.ctl, sizeof(MultiControl), stream), "clear");
+  ok(launch_multi_anchor(a, V, 0, stream), "anchor");
+  ok(launch_multi_pr(a, stream), "anchor products");
+  if (what) return fail(MBDP_ERR_HIP, "%s launch failed: %s", what, hipGetErrorString(hipGetLastError()));
+  const int64_t nb = (h->n + b - 1) / b;
+  int64_t launched = 0, recentrings = 0;
+  MultiControl ctl{};
+  uint64_t t = first_sweep;
+  while (launched < max_sweeps) {
+    const int64_t chunk = std::min<int64_t>(kMultiChunk, max_sweeps - launched);
+    for (int64_t c = 0; c < chunk && !what; ++c, ++t) {
+      for (int64_t k = 0; k < nb && !what; ++k) {
+        ok(launch_multi_gemm(a, t, k, 0, stream), "product");
+        ok(launch_multi_commit(a, t, k, 0, stream), "commit");
+      }
+      ok(launch_multi_end(a, stream), "end of sweep");
+    }
+    if (what) return fail(MBDP_ERR_HIP, "%s launch failed: %s", what, hipGetErrorString(hipGetLastError()));
+    launched += chunk;
+    MBDP_HIP(hipMemcpyAsync(&ctl, base + L.ctl, sizeof ctl, hipMemcpyDeviceToHost, stream));
+    MBDP_HIP(hipStreamSynchronize(stream));
+    if (ctl.done || launched >= max_sweeps) break;
+    if (ctl.w_bound * kMultiSplitError > kMultiErrorShare * ctl.dv_last) {
+      ok(launch_multi_anchor(a, V, 1, stream), "re-centring");
+      ok(launch_multi_pr(a, stream), "anchor products");
+      ++recentrings;
+      if (what) return fail(MBDP_ERR_HIP, "%s launch failed: %s", what, hipGetErrorString(hipGetLastError()));
+    }
+  }
+  ok(launch_multi_anchor(a, V, 2, stream), "result");
+  if (policy) {
+    for (int64_t k = 0; k < nb && !what; ++k) {
+      ok(launch_multi_gemm(a, 0, k, 1, stream), "policy product");
+      ok(launch_multi_commit(a, 0, k, 1, stream), "policy");
+    }
+  }
+  if (what) return fail(MBDP_ERR_HIP, "%s launch failed: %s", what, hipGetErrorString(hipGetLastError()));
+  MBDP_HIP(hipStreamSynchronize(stream));
+  if (stats) {
+    stats->sweeps = ctl.sweeps;
+    stats->final_dv_inf = ctl.dv_last;
+    stats->recentrings = recentrings;
+    stats->converged = ctl.done ? 1 : 0;
+    stats->reserved = 0;
+  }
+  return ctl.done || tol_dv < 0 ? MBDP_OK : MBDP_ERR_NOT_CONVERGED;
+}
+
 mbdp_status mdp_validate(mbdp_mdp_t h, double row_sum_tol, void* workspace, size_t ws_bytes,
                          hipStream_t stream, mbdp_validation* report) {
   if (!h) return fail(MBDP_ERR_INVALID_ARG, "handle is NULL");

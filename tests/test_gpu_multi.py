@@ -1,0 +1,151 @@
+"""GPU parity of the multi-vector backups (r cost vectors against one BF16
+P on the matrix cores) against the oracle's FP64 multi-vector MB-VI of the
+stored MDP: iterates after fixed sweeps from the same V0 and orders, greedy
+policies, solves to the columns' optima, ragged batches, the full-size
+shape on sampled states, and the argument checks.
+
+Tolerance of a sweep: the products see W = V - anchor as two BF16 terms
+(16 significant bits) and accumulate in FP32, so a backup is within
+gamma 2^-16 max|W| of the FP64 one (plus FP64 rounding); the test allows
+2^-16 max|V1 - V0| per sweep (the anchor is V0, W the change)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import multi as om
+from oracle import quantize as qz
+from paper_2110_02901_amd import binding as mb
+from paper_2110_02901_amd import inputs
+
+from gpu_util import check_argmin, dev, up
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print("[multi] " + msg, flush=True)
+
+
+def bf16_case(n, m, r, gamma, seed, alpha=1.0):
+    """(handle, stored P [n, m, n] FP64, C [n, m, r] FP32)."""
+    P, c = inputs.dense_mdp(n, m, alpha, seed, dtype=np.float32)
+    rows = P.reshape(n * m, n)
+    q_gpu, s_gpu = mb.mdp_quantize_rows(up(rows), "bf16")
+    h = mb.mdp_create_dense_q(q_gpu.reshape(-1), "bf16", s_gpu, up(c), gamma)
+    q_ref, s_ref = qz.quantize_rows(rows, "bf16")
+    Pst = qz.dequantized(q_ref, s_ref, "bf16").reshape(n, m, n)
+    C = inputs.multi_costs(n, m, r, seed + 7, dtype=np.float32)
+    return h, Pst, C
+
+
+def gpu_multi(h, C, V0, b, seed, first_sweep=0, tol=-1.0, max_sweeps=1, policy=True):
+    n, r = V0.shape
+    V = up(V0.copy())
+    pol = torch.zeros(n * r, dtype=torch.int32, device=dev()) if policy else None
+    ws = mb.multi_workspace(h, r, b)
+    st = mb.mdp_multi_solve(h, up(C), V, b, seed, ws, tol_dv=tol, max_sweeps=max_sweeps,
+                            first_sweep=first_sweep, policy=pol)
+    return V.cpu().numpy(), (pol.cpu().numpy().reshape(n, r) if policy else None), st
+
+
+@pytest.mark.parametrize("r", [16, 32, 48, 64])
+@pytest.mark.parametrize("b", [7, 32, 256])
+def test_sweeps_match_oracle(r, b):
+    n, m, gamma = 256, 4, 0.9
+    h, Pst, C = bf16_case(n, m, r, gamma, 3)
+    V0 = np.random.Generator(np.random.Philox(5)).uniform(0.0, 2.0, (n, r))
+    T, seed, first = 3, 11, 4
+    Vg, pol, st = gpu_multi(h, C, V0, b, seed, first_sweep=first, max_sweeps=T)
+    assert st["sweeps"] == T
+    ref, _, _, _ = om.multi_value_iteration(Pst, C.astype(np.float64), gamma, b, seed, V0=V0,
+                                            tol_dv=-1, max_sweeps=T, first_sweep=first)
+    err = float(np.max(np.abs(Vg - ref)))
+    bound = T * 2.0 ** -16 * float(np.max(np.abs(ref - V0))) + 1e-12
+    say("r=%d b=%d: max err %.3g (bound %.3g)" % (r, b, err, bound))
+    assert err <= bound
+    Q = om.multi_q_values(Pst, C.astype(np.float64), gamma, np.arange(n), Vg)
+    for j in range(r):
+        check_argmin(Q[:, :, j], pol[:, j], 1e-9)
+
+
+def test_ragged_and_tiny_shapes():
+    for (n, m, r, b) in ((32, 1, 16, 1), (96, 3, 48, 17), (160, 5, 32, 160), (64, 7, 64, 9)):
+        h, Pst, C = bf16_case(n, m, r, 0.85, 20 + n)
+        V0 = np.random.Generator(np.random.Philox(n)).uniform(-1.0, 1.0, (n, r))
+        Vg, pol, st = gpu_multi(h, C, V0, b, 3, max_sweeps=2)
+        ref, _, _, _ = om.multi_value_iteration(Pst, C.astype(np.float64), 0.85, b, 3, V0=V0,
+                                                tol_dv=-1, max_sweeps=2)
+        err = float(np.max(np.abs(Vg - ref)))
+        bound = 2 * 2.0 ** -16 * float(np.max(np.abs(ref - V0))) + 1e-12
+        say("n=%d m=%d r=%d b=%d: max err %.3g (bound %.3g)" % (n, m, r, b, err, bound))
+        assert err <= bound
+
+
+@pytest.mark.parametrize("gamma,b", [(0.9, 64), (0.99, 128)])
+def test_solves_reach_each_columns_optimum(gamma, b):
+    n, m, r = 512, 8, 32
+    h, Pst, C = bf16_case(n, m, r, gamma, 8)
+    V0 = np.zeros((n, r))
+    Vg, pol, st = gpu_multi(h, C, V0, b, 2, tol=1e-10, max_sweeps=100000)
+    say("gamma=%g b=%d: %d sweeps, %d re-centrings, dv %.3g" % (gamma, b, st["sweeps"],
+                                                                st["recentrings"], st["final_dv_inf"]))
+    assert st["converged"] and st["final_dv_inf"] <= 1e-10
+    worst = 0.0
+    for j in range(0, r, 5):
+        Vs, mu, _ = oracle.policy_iteration(oracle.DenseMDP(Pst, C[:, :, j].astype(np.float64), gamma),
+                                            improve_tol=1e-14)
+        worst = max(worst, float(np.max(np.abs(Vg[:, j] - Vs))))
+        Q = oracle.q_values(oracle.DenseMDP(Pst, C[:, :, j].astype(np.float64), gamma),
+                            np.arange(n), Vg[:, j])
+        check_argmin(Q, pol[:, j], 1e-7)
+    say("  max |V - J*| over the checked columns %.3g" % worst)
+    assert worst <= 1e-6
+    if gamma >= 0.99:
+        assert st["recentrings"] >= 1
+
+
+def test_fullsize_first_batch_sampled():
+    """n = 8192, m = 16, r = 32, BF16 Dirichlet(0.1) rows, b = 1024: one sweep
+    from a random V0; the states of the first batch read only V0, so each is
+    checked one by one against rows of the stored P."""
+    n, m, r, b, gamma = 8192, 16, 32, 1024, 0.99
+    Pfull, c = inputs.dense_mdp(n, m, 0.1, 2, dtype=np.float32)   # the benchmark's recipe
+    say("full size: generated P")
+    rows = up(Pfull.reshape(n * m, n))
+    q_gpu, s_gpu = mb.mdp_quantize_rows(rows, "bf16")
+    del rows
+    h = mb.mdp_create_dense_q(q_gpu.reshape(-1), "bf16", s_gpu, up(c), gamma)
+    C = inputs.multi_costs(n, m, r, 9, dtype=np.float32)
+    V0 = np.random.Generator(np.random.Philox(6)).uniform(5.0, 7.0, (n, r))
+    Vg, _, st = gpu_multi(h, C, V0, b, 1, max_sweeps=1, policy=False)
+    order = oracle.sweep_permutation(n, 1, 0)
+    sample = order[:b][np.random.Generator(np.random.Philox(7)).choice(b, 48, replace=False)]
+    worst = 0.0
+    for s in sample:
+        q_ref, s_ref = qz.quantize_rows(Pfull[s], "bf16")
+        Ps = qz.dequantized(q_ref, s_ref, "bf16")                 # [m, n]
+        Q = C[s].astype(np.float64) + gamma * (Ps @ V0)          # [m, r]
+        worst = max(worst, float(np.max(np.abs(Vg[s] - Q.min(axis=0)))))
+    bound = 2.0 ** -16 * float(np.max(np.abs(Vg - V0))) + 1e-12
+    say("full size: %d sampled first-batch states, max err %.3g (bound %.3g)" % (len(sample), worst, bound))
+    assert worst <= bound
+    # every state moved by a backup; all values finite
+    assert np.all(np.isfinite(Vg))
+
+
+def test_rejections():
+    h, _, C = bf16_case(64, 2, 16, 0.9, 1)
+    with pytest.raises(RuntimeError):
+        mb.multi_workspace(h, 20, 8)          # r not a multiple of 16
+    with pytest.raises(RuntimeError):
+        mb.multi_workspace(h, 16, 65)         # b > n
+    P, c = inputs.dense_mdp(64, 2, 1.0, 1, dtype=np.float32)
+    h32 = mb.mdp_create_dense(up(P), up(c), 0.9)
+    with pytest.raises(RuntimeError):
+        mb.multi_workspace(h32, 16, 8)        # FP32 storage
+    P, c = inputs.dense_mdp(72, 2, 1.0, 1, dtype=np.float32)
+    q, s = mb.mdp_quantize_rows(up(P.reshape(144, 72)), "bf16")
+    h72 = mb.mdp_create_dense_q(q.reshape(-1), "bf16", s, up(c), 0.9)
+    with pytest.raises(RuntimeError):
+        mb.multi_workspace(h72, 16, 8)        # n % 32 != 0
