@@ -105,6 +105,118 @@ def cpu_baseline(mdp, wl_name, b, seed, budget_s=20.0):
                       "%.1f s" % (sweeps, b, wl_name, n, m, dt)}
 
 
+def run_multi(args, dev):
+    """r cost vectors against the dense-8192x16 transitions stored in BF16
+    (n = 8192, m = 16, rows Dirichlet(0.1), one scale per row), C[s, a, j] ~
+    U[0, 1), gamma = 0.99, b = 1024, V0 = 0: one mdp_multi_solve until the
+    largest change of a sweep over all vectors is <= 1e-8 (so every column is
+    within 1e-8 gamma / (1 - gamma) ~ 1e-6 of its J*)."""
+    import torch
+    import oracle
+    from oracle import multi as om
+    from oracle import quantize as qz
+    from paper_2110_02901_amd import binding as mb
+    from paper_2110_02901_amd import inputs
+
+    wl = inputs.WORKLOADS["dense-8192x16"]
+    n, m, gamma, r, b, tol = wl["n"], wl["m"], wl["gamma"], args.multi_r, 1024, 1e-8
+    seed = wl["perm_seed"]
+    t0 = time.perf_counter()
+    P, c = inputs.dense_mdp(n, m, wl["alpha"], wl["data_seed"], dtype=np.float32)
+    rows = torch.from_numpy(P.reshape(n * m, n)).to(dev)
+    codes, rscale = mb.mdp_quantize_rows(rows, "bf16")
+    del rows
+    h = mb.mdp_create_dense_q(codes.reshape(-1), "bf16", rscale, torch.from_numpy(c).to(dev), gamma)
+    C = inputs.multi_costs(n, m, r, wl["data_seed"] + 100, dtype=np.float32)
+    Cd = torch.from_numpy(C).to(dev)
+    ws = mb.multi_workspace(h, r, b)
+    log("multi-%dx%d: P in BF16 (%.2f GB), r = %d cost vectors, ready in %.1f s"
+        % (n, m, codes.numel() * 2 / 1e9, r, time.perf_counter() - t0))
+    V = torch.zeros(n, r, dtype=torch.float64, device=dev)
+
+    def solve():
+        V.zero_()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record()
+        st = mb.mdp_multi_solve(h, Cd, V, b, seed, ws, tol_dv=tol, max_sweeps=100000)
+        e1.record()
+        e1.synchronize()
+        return st, e0.elapsed_time(e1) / 1e3, time.perf_counter() - w0
+
+    for _ in range(args.warmup):
+        solve()
+    walls, gpus = [], []
+    for _ in range(args.steps):
+        st, g, w = solve()
+        gpus.append(g)
+        walls.append(w)
+    if not st["converged"]:
+        raise RuntimeError("multi-vector solve did not converge")
+    sweeps = st["sweeps"]
+    # per sweep of the single-vector BF16 kernel on the same handle, for comparison
+    V1 = torch.zeros(n, dtype=torch.float32, device=dev)
+    ws1 = mb.workspace(h, n)
+    mb.vi_solve(h, V1, b, seed, ws1, tol_dv=-1.0, max_sweeps=5)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    mb.vi_solve(h, V1, b, seed, ws1, tol_dv=-1.0, max_sweeps=40)
+    e1.record()
+    e1.synchronize()
+    single_sweep_s = e0.elapsed_time(e1) / 1e3 / 40
+    wall = float(np.mean(walls))
+    gpu = float(np.mean(gpus))
+    backups = sweeps * n * m * r
+    bytes_sweep = n * m * (2 * n + 4) + n * m * r * 4 + n * r * 16
+    gbps = sweeps * bytes_sweep / gpu / 1e9
+    tflops = sweeps * 2.0 * 2 * n * m * n * r / gpu / 1e12  # two BF16 terms of W
+    log("multi r=%d: %d sweeps, %d re-centrings, %.1f ms (%.3f ms per sweep; single-vector "
+        "BF16 sweep %.3f ms, so %.1fx the backups per second of r single-vector solves)"
+        % (r, sweeps, st["recentrings"], gpu * 1e3, gpu / sweeps * 1e3, single_sweep_s * 1e3,
+           r * single_sweep_s / (gpu / sweeps)))
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's backups of a sample of states against the same stored rows
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max((t.get("num_threads", 1) for t in threadpool_info()), default=1)
+        except Exception:
+            cores = 1
+        sample = oracle.sweep_permutation(n, seed, 0)[:64]
+        q_ref, s_ref = qz.quantize_rows(P[sample].reshape(-1, n), "bf16")
+        Ps = qz.dequantized(q_ref, s_ref, "bf16").reshape(len(sample), m, n)
+        Vh = np.random.Generator(np.random.Philox(1)).random((n, r))
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 10.0:
+            om.multi_q_values(Ps, C[sample].astype(np.float64), gamma,
+                              np.arange(len(sample)), Vh).min(axis=1)
+            reps += 1
+        dt = time.perf_counter() - t0
+        cpu = {"value": reps * len(sample) * m * r / dt, "unit": "backups/s", "cores": int(cores),
+               "kind": "oracle",
+               "sample": "%d x the FP64 multi-vector backups of 64 states (m = %d, r = %d) against "
+                         "their stored BF16 rows, %.1f s" % (reps, m, r, dt)}
+    line = {
+        "metric": METRIC, "value": backups / wall, "unit": "backups/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "multi-8192x16", "n": n, "m": m, "r": r, "alpha": wl["alpha"],
+                   "gamma": gamma, "b": b, "storage": "bf16", "tol_dv": tol},
+        "sweeps": sweeps, "recentrings": st["recentrings"], "solve_ms": gpu * 1e3,
+        "single_vector_sweep_ms": single_sweep_s * 1e3, "mfma_tflops": tflops,
+        "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "multi_gemm_kernel + multi_commit_kernel (whole solve)",
+                     "algorithmic_bytes_per_backup": "(2 n + 4) / r + 4 + 16 / m"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def run_batch(args, dev):
     """512 independent dense MDPs, n ~ U[256, 4096], m = 8, Dirichlet(1) rows in
     BF16 with one scale per row, c ~ U[0, 1), gamma ~ U[0.9, 0.99], b =
@@ -254,7 +366,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dense-8192x16",
-                    choices=["dense-8192x16", "csr-1M-banded", "csr-1M-uniform", "batch-512"])
+                    choices=["dense-8192x16", "csr-1M-banded", "csr-1M-uniform", "batch-512",
+                             "multi-8192x16"])
+    ap.add_argument("--multi-r", type=int, default=32, choices=[16, 32, 48, 64],
+                    help="multi-8192x16: number of cost vectors")
     ap.add_argument("--no-tune", action="store_true",
                     help="batch-512: keep the default lane-group widths")
     ap.add_argument("--batch-sizes", default=None,
@@ -300,6 +415,9 @@ def main():
     wl_name = args.workload
     if wl_name == "batch-512":
         run_batch(args, dev)
+        return
+    if wl_name == "multi-8192x16":
+        run_multi(args, dev)
         return
     wl = inputs.WORKLOADS[wl_name]
     n, m, gamma = wl["n"], wl["m"], wl["gamma"]

@@ -66,7 +66,7 @@ __device__ __forceinline__ void multi_row_state(int64_t row, int32_t m, int full
 // range of code(row, k) * (hi + lo)(k, j).  A wavefront owns 16 RT rows and
 // all NCT * 16 vectors; lane l feeds rows l % 16 of each row tile and vectors
 // l % 16 of each column tile, 8 consecutive k from 8 (l / 16).
-template <int RT, int NCT>
+template <int RT, int NCT, int U>
 __global__ void __launch_bounds__(256) multi_gemm_kernel(MultiArgs A, uint64_t t, int64_t k,
                                                          int full) {
   if (!full && multi_done(A.ctl)) return;
@@ -103,7 +103,36 @@ __global__ void __launch_bounds__(256) multi_gemm_kernel(MultiArgs A, uint64_t t
     for (int c = 0; c < NCT; ++c) acc[rt][c] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int64_t k0 = (int64_t)blockIdx.y * A.kchunk;
   const int64_t k1 = min(n, k0 + A.kchunk);
-  for (int64_t kk = k0; kk < k1; kk += 32) {
+  // U steps of 32 per round, every load of the round issued before its
+  // products, so each wavefront keeps U row pieces in flight
+  int64_t kk = k0;
+  for (; kk + 32 * U <= k1; kk += 32 * U) {
+    u32x4 av[U][RT], bv[U][NCT][2];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+        av[u][rt] = __builtin_nontemporal_load((const MBDP_GLOBAL u32x4*)(arow[rt] + kk + 32 * u));
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < NCT; ++c)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          bv[u][c][h] = *(const MBDP_GLOBAL u32x4*)(bcol[c][h] + kk + 32 * u);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int c = 0; c < NCT; ++c)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            acc[rt][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                __builtin_bit_cast(bf16x8, av[u][rt]), __builtin_bit_cast(bf16x8, bv[u][c][h]),
+                acc[rt][c], 0, 0, 0);
+  }
+  for (; kk < k1; kk += 32) {
     u32x4 av[RT], bv[NCT][2];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
@@ -152,17 +181,29 @@ __global__ void __launch_bounds__(256) multi_commit_kernel(MultiArgs A, uint64_t
     const int64_t s = mode ? kb + p : (int64_t)sweep_order_at((uint32_t)(kb + p), key);
     double best = INFINITY;
     int32_t besta = 0;
-    for (int32_t a = 0; a < A.m; ++a) {
-      const int64_t lrow = p * A.m + a;      // row of the launch
-      const int64_t grow = s * A.m + a;      // row of P
-      double acc = 0.0;
-      for (int sp = 0; sp < A.splits; ++sp)
-        acc += (double)A.part[((size_t)sp * A.part_rows + lrow) * A.r + j];
-      const double q = (double)A.C[(size_t)grow * A.r + j] +
-                       A.gamma * ((double)A.rscale[grow] * acc + A.PR[(size_t)grow * A.r + j]);
-      if (q < best) {  // strictly smaller keeps the lowest action on ties
-        best = q;
-        besta = a;
+    // 8 actions at a time, all their operands loaded before the minimum
+    for (int32_t a0 = 0; a0 < A.m; a0 += 8) {
+      double acc[8], cst[8], pr[8], sc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int32_t a = min(a0 + u, A.m - 1);
+        const int64_t lrow = p * A.m + a;      // row of the launch
+        const int64_t grow = s * A.m + a;      // row of P
+        cst[u] = (double)A.C[(size_t)grow * A.r + j];
+        pr[u] = A.PR[(size_t)grow * A.r + j];
+        sc[u] = (double)A.rscale[grow];
+        acc[u] = 0.0;
+#pragma unroll 4
+        for (int sp = 0; sp < A.splits; ++sp)
+          acc[u] += (double)A.part[((size_t)sp * A.part_rows + lrow) * A.r + j];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double q = cst[u] + A.gamma * (sc[u] * acc[u] + pr[u]);
+        if (a0 + u < A.m && q < best) {  // strictly smaller keeps the lowest action on ties
+          best = q;
+          besta = a0 + u;
+        }
       }
     }
     if (mode == 1) {
@@ -280,10 +321,10 @@ typedef void (*MultiGemmFn)(MultiArgs, uint64_t, int64_t, int);
 
 static MultiGemmFn multi_gemm_fn(int32_t r) {
   switch (r) {
-    case 16: return multi_gemm_kernel<1, 1>;
-    case 32: return multi_gemm_kernel<2, 2>;
-    case 48: return multi_gemm_kernel<3, 3>;
-    case 64: return multi_gemm_kernel<4, 4>;
+    case 16: return multi_gemm_kernel<1, 1, 4>;
+    case 32: return multi_gemm_kernel<2, 2, 4>;
+    case 48: return multi_gemm_kernel<3, 3, 2>;
+    case 64: return multi_gemm_kernel<4, 4, 2>;
     default: return nullptr;
   }
 }
