@@ -133,6 +133,17 @@ def run_multi(args, dev):
     log("multi-%dx%d: P in BF16 (%.2f GB), r = %d cost vectors, ready in %.1f s"
         % (n, m, codes.numel() * 2 / 1e9, r, time.perf_counter() - t0))
     V = torch.zeros(n, r, dtype=torch.float64, device=dev)
+    bytes_sweep = n * m * (2 * n + 4) + n * m * r * 4 + n * r * 16
+    if args.profile_sweeps:
+        # counter runs: solves of exactly S and 3S sweeps, each after a fill of V
+        out = {"workload": "multi-8192x16", "r": r, "b": b, "launches": [],
+               "sources_hash": sources_hash("multi"), "algorithmic_bytes_per_sweep": bytes_sweep}
+        for sweeps in (args.profile_sweeps, 3 * args.profile_sweeps):
+            V.zero_()
+            st = mb.mdp_multi_solve(h, Cd, V, b, seed, ws, tol_dv=-1.0, max_sweeps=sweeps)
+            out["launches"].append({"sweeps": st["sweeps"], "recentrings": st["recentrings"]})
+        print(json.dumps(out), flush=True)
+        return
 
     def solve():
         V.zero_()
@@ -170,8 +181,14 @@ def run_multi(args, dev):
     wall = float(np.mean(walls))
     gpu = float(np.mean(gpus))
     backups = sweeps * n * m * r
-    bytes_sweep = n * m * (2 * n + 4) + n * m * r * 4 + n * r * 16
     gbps = sweeps * bytes_sweep / gpu / 1e9
+    traffic = None
+    vals = _traffic_file("multi-8192x16-r%d" % r)
+    if vals.get("sources_hash") == sources_hash("multi"):
+        try:
+            traffic = sweeps * float(vals["hbm_bytes_per_sweep"]) + float(vals["hbm_bytes_prologue"])
+        except (KeyError, ValueError):
+            traffic = None
     tflops = sweeps * 2.0 * 2 * n * m * n * r / gpu / 1e12  # two BF16 terms of W
     log("multi r=%d: %d sweeps, %d re-centrings, %.1f ms (%.3f ms per sweep; single-vector "
         "BF16 sweep %.3f ms, so %.1fx the backups per second of r single-vector solves)"
@@ -209,7 +226,7 @@ def run_multi(args, dev):
         "sweeps": sweeps, "recentrings": st["recentrings"], "solve_ms": gpu * 1e3,
         "single_vector_sweep_ms": single_sweep_s * 1e3, "mfma_tflops": tflops,
         "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": gbps / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": "multi_gemm_kernel + multi_commit_kernel (whole solve)",
                      "algorithmic_bytes_per_backup": "(2 n + 4) / r + 4 + 16 / m"},
         "cpu_baseline": cpu,
