@@ -65,16 +65,31 @@ __device__ __forceinline__ void multi_row_state(int64_t row, int32_t m, int full
 // Partial products of one K-range: part[split][row][j] = sum over k in the
 // range of code(row, k) * (hi + lo)(k, j).  A wavefront owns 16 RT rows and
 // all NCT * 16 vectors; lane l feeds rows l % 16 of each row tile and vectors
-// l % 16 of each column tile, 8 consecutive k from 8 (l / 16).
-template <int RT, int NCT, int U>
+// l % 16 of each column tile, 8 consecutive k from 8 (l / 16) (the same k map
+// for both operands).  K runs in rounds: the rows come straight from
+// HBM (every load of a round issued before its products), while the W terms
+// of the round, shared by the workgroup's four wavefronts, are staged in LDS
+// once per workgroup with whole-line loads (double buffered: the next
+// round's W is fetched during this round's products).  Reading W per
+// wavefront from L2 in 64-byte pieces cost more than the row stream itself.
+// Rounds are 128 wide up to 32 vectors, 64 wide above (registers).
+template <int RT, int NCT, int ROUND>  // ROUND: K per round (64 or 128)
 __global__ void __launch_bounds__(256) multi_gemm_kernel(MultiArgs A, uint64_t t, int64_t k,
                                                          int full) {
-  if (!full && multi_done(A.ctl)) return;
+  constexpr int U = ROUND / 32;
+  constexpr int PITCH = ROUND + 8;                     // staged W row, 16-byte pad
+  constexpr int PPR = ROUND / 8;                       // 16-byte pieces per staged row
+  constexpr int WROWS = 2 * NCT * 16;                  // staged W rows: 2 terms x r vectors
+  constexpr int WPIECES = WROWS * PPR;                 // pieces per round
+  constexpr int WPER = (WPIECES + 255) / 256;          // per thread
+  __shared__ __attribute__((aligned(16))) uint16_t Wl[2][WROWS][PITCH];
+  if (!full && multi_done(A.ctl)) return;  // uniform over the launch
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t kb = k * A.b;
   const int64_t rows = min(A.b, A.n - kb) * A.m;
-  const int64_t tile0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * RT);
-  if (tile0 >= rows) return;
+  const int64_t wg0 = (int64_t)blockIdx.x * 4 * (16 * RT);
+  if (wg0 >= rows) return;  // whole workgroup: no barrier is skipped by part of it
+  const int64_t tile0 = wg0 + wave * (16 * RT);
   const OrderKey key = make_order_key(A.n, A.seed, t);
   const int i = lane & 15, g = lane >> 4;
   const int64_t n = A.n;
@@ -90,12 +105,6 @@ __global__ void __launch_bounds__(256) multi_gemm_kernel(MultiArgs A, uint64_t t
     multi_row_state(row, A.m, full, kb, key, s, a);
     arow[rt] = P + ((size_t)s * A.m + a) * (size_t)n + 8 * g;
   }
-  const MBDP_GLOBAL uint16_t* bcol[NCT][2];
-#pragma unroll
-  for (int c = 0; c < NCT; ++c)
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-      bcol[c][h] = Ws + ((size_t)h * A.r + c * 16 + i) * (size_t)n + 8 * g;
   f32x4 acc[RT][NCT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
@@ -103,54 +112,68 @@ __global__ void __launch_bounds__(256) multi_gemm_kernel(MultiArgs A, uint64_t t
     for (int c = 0; c < NCT; ++c) acc[rt][c] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int64_t k0 = (int64_t)blockIdx.y * A.kchunk;
   const int64_t k1 = min(n, k0 + A.kchunk);
-  // U steps of 32 per round, every load of the round issued before its
-  // products, so each wavefront keeps U row pieces in flight
-  int64_t kk = k0;
-  for (; kk + 32 * U <= k1; kk += 32 * U) {
-    u32x4 av[U][RT], bv[U][NCT][2];
+  // staged W row w = h * r + j holds W term h of vector j; piece q of a round
+  // is row q / PPR, values 8 (q % PPR) .. +7
+  auto fetch_w = [&](int64_t kk, u32x4 (&wr)[WPER]) {
+#pragma unroll
+    for (int e = 0; e < WPER; ++e) {
+      const int q = threadIdx.x + 256 * e;
+      const int w = q / PPR, c8 = (q % PPR) * 8;
+      if (q < WPIECES && kk + c8 < k1) {
+        const int h = w / (NCT * 16), j = w - h * (NCT * 16);
+        wr[e] = *(const MBDP_GLOBAL u32x4*)(Ws + ((size_t)h * A.r + j) * (size_t)n + kk + c8);
+      } else {
+        wr[e] = u32x4{0u, 0u, 0u, 0u};
+      }
+    }
+  };
+  auto store_w = [&](int buf, const u32x4 (&wr)[WPER]) {
+#pragma unroll
+    for (int e = 0; e < WPER; ++e) {
+      const int q = threadIdx.x + 256 * e;
+      if (q < WPIECES) *(u32x4*)&Wl[buf][q / PPR][(q % PPR) * 8] = wr[e];
+    }
+  };
+  {
+    u32x4 wr[WPER];
+    fetch_w(k0, wr);
+    store_w(0, wr);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t kk = k0; kk < k1; kk += ROUND, buf ^= 1) {
+    const int steps = (int)min((int64_t)U, (k1 - kk) / 32);  // last round may be short
+    u32x4 av[U][RT];
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
-        av[u][rt] = __builtin_nontemporal_load((const MBDP_GLOBAL u32x4*)(arow[rt] + kk + 32 * u));
+        av[u][rt] = u < steps ? __builtin_nontemporal_load(
+                                    (const MBDP_GLOBAL u32x4*)(arow[rt] + kk + 32 * u))
+                              : u32x4{0u, 0u, 0u, 0u};
+    const bool next = kk + ROUND < k1;
+    u32x4 wr[WPER];
+    if (next) fetch_w(kk + ROUND, wr);
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int u = 0; u < U; ++u) {
+      if (u >= steps) break;
 #pragma unroll
       for (int c = 0; c < NCT; ++c)
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-          bv[u][c][h] = *(const MBDP_GLOBAL u32x4*)(bcol[c][h] + kk + 32 * u);
+        for (int h = 0; h < 2; ++h) {
+          const u32x4 bv = *(const u32x4*)&Wl[buf][h * NCT * 16 + c * 16 + i][32 * u + 8 * g];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int c = 0; c < NCT; ++c)
-#pragma unroll
-          for (int h = 0; h < 2; ++h)
+          for (int rt = 0; rt < RT; ++rt)
             acc[rt][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                __builtin_bit_cast(bf16x8, av[u][rt]), __builtin_bit_cast(bf16x8, bv[u][c][h]),
-                acc[rt][c], 0, 0, 0);
+                __builtin_bit_cast(bf16x8, av[u][rt]), __builtin_bit_cast(bf16x8, bv), acc[rt][c],
+                0, 0, 0);
+        }
+    }
+    // the other buffer was last read in the previous round, before its barrier
+    if (next) store_w(buf ^ 1, wr);
+    __syncthreads();
   }
-  for (; kk < k1; kk += 32) {
-    u32x4 av[RT], bv[NCT][2];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-      av[rt] = __builtin_nontemporal_load((const MBDP_GLOBAL u32x4*)(arow[rt] + kk));
-#pragma unroll
-    for (int c = 0; c < NCT; ++c)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) bv[c][h] = *(const MBDP_GLOBAL u32x4*)(bcol[c][h] + kk);
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int c = 0; c < NCT; ++c)
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-          acc[rt][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              __builtin_bit_cast(bf16x8, av[rt]), __builtin_bit_cast(bf16x8, bv[c][h]),
-              acc[rt][c], 0, 0, 0);
-  }
+  if (tile0 >= rows) return;  // after the last barrier
   // lane l holds rows 4 (l / 16) + v of each 16-row tile, vector l % 16 of each column tile
   MBDP_GLOBAL float* part = (MBDP_GLOBAL float*)A.part + (size_t)blockIdx.y * A.part_rows * A.r;
 #pragma unroll
@@ -321,10 +344,10 @@ typedef void (*MultiGemmFn)(MultiArgs, uint64_t, int64_t, int);
 
 static MultiGemmFn multi_gemm_fn(int32_t r) {
   switch (r) {
-    case 16: return multi_gemm_kernel<1, 1, 4>;
-    case 32: return multi_gemm_kernel<2, 2, 4>;
-    case 48: return multi_gemm_kernel<3, 3, 2>;
-    case 64: return multi_gemm_kernel<4, 4, 2>;
+    case 16: return multi_gemm_kernel<1, 1, 128>;
+    case 32: return multi_gemm_kernel<2, 2, 128>;
+    case 48: return multi_gemm_kernel<3, 3, 64>;
+    case 64: return multi_gemm_kernel<4, 4, 64>;
     default: return nullptr;
   }
 }
