@@ -257,7 +257,7 @@ int launch_batch(const BatchArgs& a, int blocks, void* stream);
 constexpr int32_t kMultiMaxR = 64;
 
 struct MultiControl {
-  unsigned long long dv_bits;  // max |dV| of the sweep in progress (bits of a non-negative double)
+  unsigned long long unused;
   double dv_last;              // max |dV| of the last completed sweep
   double w_bound;              // sum of the sweeps' max |dV| since the last re-centring (>= max |W|)
   long long sweeps;            // sweeps completed
@@ -284,6 +284,7 @@ struct MultiArgs {
   int64_t kchunk;        // K per split, a multiple of 32
   int32_t splits;
   int32_t* policy;       // [n][r] or null
+  double* dvs;           // [n] max |dV| over the vectors per position of the sweep
   MultiControl* ctl;
 };
 
@@ -291,7 +292,7 @@ struct MultiArgs {
 inline int64_t multi_rows_per_wave(int32_t r) { return r; }
 
 struct MultiLayout {
-  size_t ctl, R, W, Ws, PR, part, total;
+  size_t ctl, R, W, Ws, PR, part, dvs, total;
   int64_t kchunk;
   int32_t splits;
 };
@@ -313,6 +314,7 @@ inline MultiLayout multi_layout(int64_t n, int32_t m, int32_t r, int64_t b) {
   l.Ws = off;   off = align_up(off + 2 * (size_t)r * n * sizeof(uint16_t), 256);
   l.PR = off;   off = align_up(off + (size_t)n * m * r * sizeof(double), 256);
   l.part = off; off = align_up(off + (size_t)l.splits * b * m * r * sizeof(float), 256);
+  l.dvs = off;  off = align_up(off + (size_t)n * sizeof(double), 256);
   l.total = off;
   return l;
 }

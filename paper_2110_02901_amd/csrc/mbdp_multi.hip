@@ -21,7 +21,7 @@
 // thousand rows still fills the device), `multi_commit_kernel` adds the
 // partials in FP64 with the cost, the anchor share and the row scale, takes
 // the minimum over actions and commits the batch.  `multi_end_kernel` closes
-// a sweep (its max |dV|, the stop flag).  Every kernel returns at once when
+// a sweep (its max |dV| from the commits' per-position maxima, the stop flag).  Every kernel returns at once when
 // the stop flag is set, so the host can enqueue several sweeps and read the
 // control block once.
 
@@ -189,44 +189,49 @@ __global__ void __launch_bounds__(256) multi_gemm_kernel(MultiArgs A, uint64_t t
 }
 
 // Commit of batch k (mode 0), or the greedy action of states kb .. kb + b - 1
-// (mode 1): a thread per (state of the launch, vector).
+// (mode 1): a workgroup per state.  Thread (al, j) serves vector j and the
+// actions a = al, al + AL, ... (AL = 256 / r action lanes); the lanes' minima
+// meet in LDS, lowest action on ties.
 __global__ void __launch_bounds__(256) multi_commit_kernel(MultiArgs A, uint64_t t, int64_t k,
                                                            int mode) {
-  if (mode == 0 && multi_done(A.ctl)) return;
+  __shared__ double qs[256];
+  __shared__ int32_t as[256];
+  if (mode == 0 && multi_done(A.ctl)) return;  // uniform over the launch
   const int64_t kb = k * A.b;
-  const int64_t states = min(A.b, A.n - kb);
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double dv = 0.0;
-  if (idx < states * A.r) {
-    const OrderKey key = make_order_key(A.n, A.seed, t);
-    const int64_t p = idx / A.r;
-    const int32_t j = (int32_t)(idx - p * A.r);
-    const int64_t s = mode ? kb + p : (int64_t)sweep_order_at((uint32_t)(kb + p), key);
-    double best = INFINITY;
-    int32_t besta = 0;
-    // 8 actions at a time, all their operands loaded before the minimum
-    for (int32_t a0 = 0; a0 < A.m; a0 += 8) {
-      double acc[8], cst[8], pr[8], sc[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int32_t a = min(a0 + u, A.m - 1);
-        const int64_t lrow = p * A.m + a;      // row of the launch
-        const int64_t grow = s * A.m + a;      // row of P
-        cst[u] = (double)A.C[(size_t)grow * A.r + j];
-        pr[u] = A.PR[(size_t)grow * A.r + j];
-        sc[u] = (double)A.rscale[grow];
-        acc[u] = 0.0;
+  const int64_t p = blockIdx.x;                // position in the launch (< min(b, n - kb))
+  const int AL = 256 / A.r;
+  const int al = threadIdx.x / A.r, j = threadIdx.x - al * A.r;
+  const OrderKey key = make_order_key(A.n, A.seed, t);
+  const int64_t s = mode ? kb + p : (int64_t)sweep_order_at((uint32_t)(kb + p), key);
+  double best = INFINITY;
+  int32_t besta = 0;
+  if (al < AL) {
+    for (int32_t a = al; a < A.m; a += AL) {
+      const int64_t lrow = p * A.m + a;      // row of the launch
+      const int64_t grow = s * A.m + a;      // row of P
+      double acc = 0.0;
 #pragma unroll 4
-        for (int sp = 0; sp < A.splits; ++sp)
-          acc[u] += (double)A.part[((size_t)sp * A.part_rows + lrow) * A.r + j];
+      for (int sp = 0; sp < A.splits; ++sp)
+        acc += (double)A.part[((size_t)sp * A.part_rows + lrow) * A.r + j];
+      const double q = (double)A.C[(size_t)grow * A.r + j] +
+                       A.gamma * ((double)A.rscale[grow] * acc + A.PR[(size_t)grow * A.r + j]);
+      if (q < best) {  // ascending actions: strictly smaller keeps the lowest
+        best = q;
+        besta = a;
       }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const double q = cst[u] + A.gamma * (sc[u] * acc[u] + pr[u]);
-        if (a0 + u < A.m && q < best) {  // strictly smaller keeps the lowest action on ties
-          best = q;
-          besta = a0 + u;
-        }
+    }
+  }
+  qs[threadIdx.x] = best;
+  as[threadIdx.x] = besta;
+  __syncthreads();
+  double dv = 0.0;
+  if (al == 0) {
+    for (int l = 1; l < AL; ++l) {
+      const double q2 = qs[l * A.r + j];
+      const int32_t a2 = as[l * A.r + j];
+      if (q2 < best || (q2 == best && a2 < besta)) {
+        best = q2;
+        besta = a2;
       }
     }
     if (mode == 1) {
@@ -242,19 +247,27 @@ __global__ void __launch_bounds__(256) multi_commit_kernel(MultiArgs A, uint64_t
       A.Ws[((size_t)A.r + j) * A.n + s] = (uint16_t)lo;
     }
   }
-  if (mode == 0) {
+  if (mode == 0 && threadIdx.x < 64) {  // the r <= 64 threads with al == 0 are in wavefront 0
     dv = wave_max_d(dv);
-    if ((threadIdx.x & 63) == 0 && dv > 0.0)  // non-negative doubles order as their bits
-      atomicMax(&A.ctl->dv_bits, (unsigned long long)__double_as_longlong(dv));
+    // one slot per position of the sweep (every sweep writes all n), reduced
+    // by the end-of-sweep kernel: no contended atomic per workgroup
+    if (threadIdx.x == 0) A.dvs[kb + p] = dv;
   }
 }
 
-// End of sweep t: its max |dV|, the bound on max |W|, the stop flag.
-__global__ void multi_end_kernel(MultiArgs A) {
-  if (threadIdx.x != 0 || multi_done(A.ctl)) return;
+// End of sweep t: its max |dV| (over the per-position maxima the commits
+// wrote), the bound on max |W|, the stop flag.  One workgroup.
+__global__ void __launch_bounds__(256) multi_end_kernel(MultiArgs A) {
+  __shared__ double red[4];
+  if (multi_done(A.ctl)) return;  // uniform over the workgroup
+  double dv = 0.0;
+  for (int64_t e = threadIdx.x; e < A.n; e += blockDim.x) dv = fmax(dv, A.dvs[e]);
+  dv = wave_max_d(dv);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dv;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  dv = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   MultiControl* c = A.ctl;
-  const double dv = __longlong_as_double((long long)c->dv_bits);
-  c->dv_bits = 0ull;
   c->dv_last = dv;
   c->w_bound += dv;
   c->sweeps += 1;
@@ -366,15 +379,14 @@ int launch_multi_gemm(const MultiArgs& a, uint64_t t, int64_t k, int full, void*
 }
 
 int launch_multi_commit(const MultiArgs& a, uint64_t t, int64_t k, int mode, void* stream) {
-  const int64_t states = std::min<int64_t>(a.b, a.n - k * a.b);
-  const int64_t blocks = (states * a.r + 255) / 256;
+  const int64_t blocks = std::min<int64_t>(a.b, a.n - k * a.b);  // a workgroup per state
   hipLaunchKernelGGL(multi_commit_kernel, dim3((unsigned)blocks), dim3(256), 0,
                      reinterpret_cast<hipStream_t>(stream), a, t, k, mode);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_multi_end(const MultiArgs& a, void* stream) {
-  hipLaunchKernelGGL(multi_end_kernel, dim3(1), dim3(64), 0,
+  hipLaunchKernelGGL(multi_end_kernel, dim3(1), dim3(256), 0,
                      reinterpret_cast<hipStream_t>(stream), a);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -734,6 +734,7 @@ mbdp_status mdp_multi_solve(mbdp_mdp_t h, int32_t r, const float* C, double* V, 
   a.kchunk = L.kchunk;
   a.splits = L.splits;
   a.policy = policy;
+  a.dvs = reinterpret_cast<double*>(base + L.dvs);
   a.ctl = reinterpret_cast<MultiControl*>(base + L.ctl);
   const char* what = nullptr;
   auto ok = [&](int rc, const char* name) {
