@@ -242,6 +242,7 @@ def run_batch(args, dev):
     The MDPs are drawn on the GPU (torch's seeded generator)."""
     import torch
     from paper_2110_02901_amd import binding as mb
+    from paper_2110_02901_amd import inputs
     from paper_2110_02901_amd import tune
 
     count, m, tol = 512, 8, 1e-8
@@ -355,11 +356,42 @@ def run_batch(args, dev):
         log("  n=%d gamma=%.3f team=%d sweeps=%d: %.1f .. %.1f ms"
             % (ns[i], gammas[i], st["team"], st["sweeps"], st["start_us"] / 1e3,
                st["end_us"] / 1e3))
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's FP64 MB-VI sweeps on 4 MDPs of the same sizes, drawn on the
+        # host with the same recipe and stored in BF16 by the oracle's quantiser
+        import oracle
+        from oracle import quantize as qz
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max((t.get("num_threads", 1) for t in threadpool_info()), default=1)
+        except Exception:
+            cores = 1
+        mdps = []
+        for i in range(4):
+            n = int(ns[i])
+            P, c = inputs.dense_mdp(n, m, 1.0, 600 + i, dtype=np.float32)
+            q, sc = qz.quantize_rows(P.reshape(n * m, n), "bf16")
+            mdps.append(oracle.DenseMDP(qz.dequantized(q, sc, "bf16").reshape(n, m, n), c,
+                                        float(gammas[i])))
+        Vs = [np.zeros(md.n) for md in mdps]
+        done, sw, t0 = 0, 0, time.perf_counter()
+        while time.perf_counter() - t0 < 10.0:
+            for i, md in enumerate(mdps):
+                Vs[i], _, _ = oracle.mb_sweep(md, Vs[i], (md.n + 7) // 8,
+                                              oracle.sweep_permutation(md.n, 2000 + i, sw))
+                done += md.n * m
+            sw += 1
+        dt = time.perf_counter() - t0
+        cpu = {"value": done / dt, "unit": "backups/s", "cores": int(cores), "kind": "oracle",
+               "sample": "%d FP64 sweeps of B_b on each of 4 MDPs of the workload's first sizes "
+                         "(n = %s, m = %d, b = ceil(n/8), BF16 rows), %.1f s"
+                         % (sw, ", ".join(str(int(x)) for x in ns[:4]), m, dt)}
     line = {
         "metric": METRIC, "value": backups * args.steps / wall, "unit": "backups/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64",
+        "vs_baseline": None, "dtype": "f64", "cpu_baseline": cpu,
         "data": "synthetic", "replay_ms": kernel_s / args.steps * 1e3,
         "config": {"workload": "batch-512", "count": count, "n": "U[256, 4096]", "m": m,
                    "alpha": 1.0, "gamma": "U[0.9, 0.99]", "b": "ceil(n / 8)",
