@@ -201,3 +201,45 @@ def test_batch_rejects_bad_team_sizes():
         it["team"] = bad
         with pytest.raises(RuntimeError):
             mb.mdp_batch_upload([it], ws)
+
+
+def test_batch_teams_replay_from_a_hip_graph():
+    """A captured launch with teams replays to the eager result, three times,
+    with eager work in between (the team barrier counters are cleared by a
+    fill kernel inside the capture)."""
+    specs = [(700, 8, "bf16", 0.9, 88, 16, 3), (1000, 4, "fp8", 0.95, 125, 64, 2),
+             (333, 2, "f32", 0.93, 42, 32, 1), (2048, 8, "bf16", 0.97, 256, 16, 4)]
+    batch = [make_item(n, m, dt, g, b, 800 + i, 90 + i, lanes, with_oracle=False)
+             for i, (n, m, dt, g, b, lanes, _) in enumerate(specs)]
+    items = []
+    for (it, _, V0), spec in zip(batch, specs):
+        it = dict(it)
+        it["team"] = spec[6]
+        items.append(it)
+    V0s = [x[2] for x in batch]
+    ws = mb.batch_workspace(len(items))
+    mb.mdp_batch_upload(items, ws)
+    T = 7
+    mb.mdp_batch_launch(len(items), -1.0, T, ws)
+    torch.cuda.synchronize()
+    eager = [it["V"].clone() for it in items]
+    assert [st["team"] for st in mb.mdp_batch_read_stats(ws, len(items))] == [s[6] for s in specs]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        for it, V0 in zip(items, V0s):
+            it["V"].copy_(up(V0.copy()))
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=s):
+            mb.mdp_batch_launch(len(items), -1.0, T, ws)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for it, V0 in zip(items, V0s):
+            it["V"].copy_(up(V0.copy()))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for it, ref in zip(items, eager):
+            assert torch.equal(it["V"], ref), rep
+        _ = torch.ones(1000, device=dev()).sum().item()
