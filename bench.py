@@ -279,6 +279,11 @@ def run_batch(args, dev):
         tuned = tune.tune_lanes(items)
         log("lane widths tuned in %.1f s: %s" % (time.perf_counter() - t0,
             {"%s/%d" % k: v[0] for k, v in tuned.items()}))
+    tuned_b = None
+    if args.tune_b:
+        t0 = time.perf_counter()
+        tuned_b = {"%s/%d" % k: v[0] for k, v in tune.tune_batch_size(items).items()}
+        log("batch sizes tuned in %.1f s: divisors %s" % (time.perf_counter() - t0, tuned_b))
     ws = mb.batch_workspace(count)
     mb.mdp_batch_upload(items, ws)
     if args.profile_sweeps:
@@ -394,7 +399,8 @@ def run_batch(args, dev):
         "vs_baseline": None, "dtype": "f64", "cpu_baseline": cpu,
         "data": "synthetic", "replay_ms": kernel_s / args.steps * 1e3,
         "config": {"workload": "batch-512", "count": count, "n": "U[256, 4096]", "m": m,
-                   "alpha": 1.0, "gamma": "U[0.9, 0.99]", "b": "ceil(n / 8)",
+                   "alpha": 1.0, "gamma": "U[0.9, 0.99]",
+                   "b": "ceil(n / 8)" if tuned_b is None else "ceil(n / d), d tuned: %s" % tuned_b,
                    "storage": "bf16", "tol_dv": tol, "launch": "hipGraph replay"},
         "hbm_gbps": gbps,
         "sweeps": {"min": min(sweeps), "max": max(sweeps), "mean": float(np.mean(sweeps))},
@@ -421,6 +427,9 @@ def main():
                     help="multi-8192x16: number of cost vectors")
     ap.add_argument("--no-tune", action="store_true",
                     help="batch-512: keep the default lane-group widths")
+    ap.add_argument("--tune-b", action="store_true",
+                    help="batch-512: let the autotuner pick b = ceil(n / d) per size class "
+                         "instead of the workload's ceil(n / 8)")
     ap.add_argument("--batch-sizes", default=None,
                     help="comma-separated batch sizes (default: the workload's)")
     ap.add_argument("--eps", type=float, default=1e-6)

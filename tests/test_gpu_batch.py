@@ -243,3 +243,30 @@ def test_batch_teams_replay_from_a_hip_graph():
         for it, ref in zip(items, eager):
             assert torch.equal(it["V"], ref), rep
         _ = torch.ones(1000, device=dev()).sum().item()
+
+
+def test_batch_size_tuner_keeps_the_fixed_point():
+    """The b tuner picks a divisor per size class; the tuned solve still
+    reaches every MDP's J* (policy iteration on the stored rows), and V is
+    restored after tuning."""
+    from paper_2110_02901_amd import tune
+    specs = [(200, 4, "f32", 0.9), (260, 4, "f32", 0.95), (600, 8, "bf16", 0.9),
+             (700, 8, "bf16", 0.97), (1100, 4, "fp8", 0.9)]
+    batch = [make_item(n, m, dt, g, 8, 1500 + i, 700 + i) for i, (n, m, dt, g) in enumerate(specs)]
+    items = [x[0] for x in batch]
+    before = [it["V"].clone() for it in items]
+    choice = tune.tune_batch_size(items, tol=1e-6, sample=4)
+    say("b tuner: %s" % {"%s/%d" % k: v[0] for k, v in choice.items()})
+    for it, V in zip(items, before):
+        assert torch.equal(it["V"], V)
+        assert 1 <= it["b"] <= min(it["n"], 4096)
+        assert any(it["b"] == tune.batch_size(it["n"], d) for d in tune.DIVISORS)
+    ws = mb.batch_workspace(len(items))
+    mb.mdp_batch_upload(items, ws)
+    mb.mdp_batch_launch(len(items), 1e-11, 100000, ws)
+    stats = mb.mdp_batch_read_stats(ws, len(items))
+    for (item, mdp, _), st in zip(batch, stats):
+        assert st["converged"], st
+        Vs, _, _ = oracle.policy_iteration(mdp, improve_tol=1e-14)
+        bound = 1e-11 * item["gamma"] / (1 - item["gamma"]) + 1e-12 * float(np.max(np.abs(Vs)))
+        assert np.max(np.abs(item["V"].cpu().numpy() - Vs)) <= 10 * bound
