@@ -270,3 +270,57 @@ def test_batch_size_tuner_keeps_the_fixed_point():
         Vs, _, _ = oracle.policy_iteration(mdp, improve_tol=1e-14)
         bound = 1e-11 * item["gamma"] / (1 - item["gamma"]) + 1e-12 * float(np.max(np.abs(Vs)))
         assert np.max(np.abs(item["V"].cpu().numpy() - Vs)) <= 10 * bound
+
+
+def test_batch_512_full_size_sampled():
+    """The benchmark's batch: 512 MDPs, n ~ U[256, 4096], m = 8, Dirichlet(1)
+    rows (torch's generator on the GPU, as the benchmark draws them) in BF16,
+    gamma ~ U[0.9, 0.99], b = ceil(n/8), automatic teams; 3 sweeps, then the
+    largest, the smallest, the heaviest (served by a team) and one more MDP
+    against the oracle's MB-VI of rows it quantises itself from host copies
+    of the same FP32 rows."""
+    count, m, T = 512, 8, 3
+    g = np.random.Generator(np.random.Philox(104))
+    ns = g.integers(256, 4097, count)
+    gammas = g.uniform(0.9, 0.99, count)
+    heavy = int(np.argmax(ns.astype(np.float64) ** 2 / -np.log(gammas)))  # gets a team
+    check = {int(np.argmax(ns)), int(np.argmin(ns)), 100, heavy}
+    gen = torch.Generator(device=dev())
+    gen.manual_seed(104)
+    items, host = [], {}
+    for i in range(count):
+        n = int(ns[i])
+        ld = (n + 15) // 16 * 16
+        rows = torch.zeros(n * m, ld, dtype=torch.float32, device=dev())
+        w = torch._standard_gamma(torch.ones(n * m, n, device=dev()), generator=gen)
+        rows[:, :n] = w / w.sum(dim=1, keepdim=True)
+        del w
+        if i in check:
+            host[i] = rows.cpu().numpy()
+        codes, scale = mb.mdp_quantize_rows(rows, "bf16")
+        del rows
+        c = torch.rand(n, m, device=dev(), generator=gen)
+        items.append({"n": n, "m": m, "dtype": "bf16", "ld": ld, "P": codes.reshape(-1),
+                      "row_scale": scale, "c": c, "gamma": float(gammas[i]), "b": (n + 7) // 8,
+                      "seed": 2000 + i, "V": torch.zeros(n, dtype=torch.float64, device=dev()),
+                      "policy": None, "lanes": 0})
+    say("generated the 512 MDPs")
+    ws = mb.batch_workspace(count)
+    mb.mdp_batch_upload(items, ws)
+    mb.mdp_batch_launch(count, -1.0, T, ws)
+    stats = mb.mdp_batch_read_stats(ws, count)
+    assert all(st["sweeps"] == T for st in stats)
+    teams = [st["team"] for st in stats]
+    say("teams: %d MDPs with more than one workgroup" % sum(t > 1 for t in teams))
+    assert teams[heavy] > 1  # the heavy MDPs run as teams in this configuration
+    for i in sorted(check):
+        n, ld = int(ns[i]), items[i]["ld"]
+        q, sc = qz.quantize_rows(host[i], "bf16")
+        Pst = qz.dequantized(q, sc, "bf16").reshape(n, m, ld)[:, :, :n]
+        c = items[i]["c"].cpu().numpy().astype(np.float64)
+        mdp = oracle.DenseMDP(Pst, c, float(gammas[i]))
+        ref, _, _ = oracle.value_iteration(mdp, (n + 7) // 8, 2000 + i, V0=np.zeros(n), tol_dv=-1,
+                                           max_sweeps=T)
+        err = float(np.max(np.abs(items[i]["V"].cpu().numpy() - ref)))
+        say("item %d n=%d team=%d: max err %.3g" % (i, n, teams[i], err))
+        assert err <= 1e-11 * max(1.0, float(np.max(np.abs(ref))))
