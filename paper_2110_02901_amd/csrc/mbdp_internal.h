@@ -257,7 +257,6 @@ int launch_batch(const BatchArgs& a, int blocks, void* stream);
 constexpr int32_t kMultiMaxR = 64;
 
 struct MultiControl {
-  unsigned long long unused;
   double dv_last;              // max |dV| of the last completed sweep
   double w_bound;              // sum of the sweeps' max |dV| since the last re-centring (>= max |W|)
   long long sweeps;            // sweeps completed
