@@ -447,7 +447,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the mini-batch sweep is built and timed on a "
-              "single MI355X (multi-GPU sharding is a design note, not part of this build); "
+              "single MI355X (sharding over several GPUs is described, not implemented); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
