@@ -2,10 +2,11 @@
 
 `tune_lanes` picks the lane-group width (threads per state row).  The
 batched kernel serves a state with a group of 16, 32 or 64 lanes; the best
-width depends on the row length (ld) and the value type: too wide and lanes
-idle on short rows, too narrow and long rows take many steps per lane.  It
-times a few sweeps of each width on a sample of the MDPs of every size
-class, on the device, and writes the fastest into the items.
+width depends on the row length (ld), the value type and the batch size: too
+wide and a workgroup has few lane groups for a batch's states, too narrow
+and long rows take many steps per lane.  It times a few sweeps of each width
+on a sample of the MDPs of every size class, on the device, and writes the
+fastest into the items.
 
 `tune_batch_size` picks b = ceil(n / d) per size class from a set of
 divisors d by timing whole solves to a tolerance on a sample.  b changes the
@@ -24,16 +25,14 @@ CANDIDATES = (16, 32, 64)
 CLASSES = ((0, 512), (512, 1024), (1024, 2048), (2048, 1 << 30))
 
 
-def _time_launch(items, sweeps, ws):
+def _cu_time(items, sweeps, ws):
+    """Compute-unit milliseconds of `sweeps` sweeps of every item, one
+    workgroup per item (the sum of the solves' spans, after a warm-up)."""
     mb.mdp_batch_upload(items, ws)
     mb.mdp_batch_launch(len(items), -1.0, 1, ws)  # warm-up
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
     mb.mdp_batch_launch(len(items), -1.0, sweeps, ws)
-    e1.record()
-    e1.synchronize()
-    return e0.elapsed_time(e1)
+    stats = mb.mdp_batch_read_stats(ws, len(items))
+    return sum(st["end_us"] - st["start_us"] for st in stats) / 1e3
 
 
 def _groups(items):
@@ -45,8 +44,12 @@ def _groups(items):
 
 
 def tune_lanes(items, sweeps=3, sample=32, candidates=CANDIDATES):
-    """Sets item['lanes'] for every item; returns {(dtype, class): (lanes, ms by width)}."""
-    saved = [it["V"].clone() for it in items]
+    """Sets item['lanes'] for every item: per size class the width with the
+    least compute-unit time for a few sweeps of up to `sample` MDPs of the
+    class, run one workgroup per MDP as most MDPs of a large batch are (a
+    few MDPs alone on the device would get teams, which change the balance).
+    Returns {(dtype, class): (lanes, compute-unit ms by width)}."""
+    saved = [(it["V"].clone(), it.get("team", 0)) for it in items]
     choice = {}
     try:
         for key, group in sorted(_groups(items).items()):
@@ -56,14 +59,16 @@ def tune_lanes(items, sweeps=3, sample=32, candidates=CANDIDATES):
             for lanes in candidates:
                 for it in probe:
                     it["lanes"] = lanes
-                times[lanes] = _time_launch(probe, sweeps, ws)
+                    it["team"] = 1
+                times[lanes] = _cu_time(probe, sweeps, ws)
             best = min(times, key=times.get)
             for it in group:
                 it["lanes"] = best
             choice[key] = (best, times)
     finally:
-        for it, V in zip(items, saved):
+        for it, (V, team) in zip(items, saved):
             it["V"].copy_(V)
+            it["team"] = team
     return choice
 
 
