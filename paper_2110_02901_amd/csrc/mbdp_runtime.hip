@@ -528,8 +528,8 @@ mbdp_status mdp_batch_upload(const mbdp_batch_item* items, int32_t count, void* 
   }
   // Team sizes.  An MDP whose work exceeds the device's fair share (total
   // work / compute units) gets that many workgroups, at most kBatchMaxTeam
-  // and at most one per lane-group-width of its batch; all members of all
-  // teams must fit on the device at once (one workgroup per compute unit).
+  // and at most 2 b / (lane groups per workgroup); all members of all teams
+  // must fit on the device at once (one workgroup per compute unit).
   int device = 0, cus = 0;
   MBDP_HIP(hipGetDevice(&device));
   MBDP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
@@ -547,8 +547,11 @@ mbdp_status mdp_batch_upload(const mbdp_batch_item* items, int32_t count, void* 
     BatchItem& b = table[(size_t)i];
     if (b.team != 0 || cus < 2 * kBatchMaxTeam) continue;
     const int64_t groups = 1024 / b.lanes;
-    int64_t k = (int64_t)ceil(work[(size_t)i] / share);
-    const int64_t kcap = std::min<int64_t>(kBatchMaxTeam, std::max<int64_t>(1, b.b / groups));
+    // a team runs below one workgroup's rate per member (team barriers), so
+    // it gets half again its share, to end with the rest of the launch
+    int64_t k = (int64_t)ceil(1.5 * work[(size_t)i] / share);
+    // at least half a state per lane group of each member per batch
+    const int64_t kcap = std::min<int64_t>(kBatchMaxTeam, std::max<int64_t>(1, 2 * b.b / groups));
     b.team = (int32_t)std::max<int64_t>(1, std::min(k, kcap));
   }
   for (int32_t i = 0; i < count; ++i) {
