@@ -29,6 +29,10 @@ Lygeros; arXiv 2110.02901):
 * ``quantize``    -- BF16 / FP8 E4M3 storage of transition rows with one
                      scale per row renormalising it to sum 1 (the reduced-
                      precision variant; the paper fixes no precision).
+* ``refine``      -- the certified FP64 correction that closes the gap between
+                     the stored MDP's solution and the given MDP's: the input
+                     residual max|TV - V| and mini-batch sweeps until the
+                     contraction bound (Sec. III-B) certifies eps.
 
 Notation: the paper's batch size ``m`` is called ``b`` here, because ``m`` is
 the number of actions; the paper's cost-to-go ``J`` is ``V`` and its discount
