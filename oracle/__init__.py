@@ -32,7 +32,8 @@ Lygeros; arXiv 2110.02901):
 * ``refine``      -- the certified FP64 correction that closes the gap between
                      the stored MDP's solution and the given MDP's: the input
                      residual max|TV - V| and mini-batch sweeps until the
-                     contraction bound (Sec. III-B) certifies eps.
+                     contraction bound (Sec. III-B) certifies eps, or the
+                     same by Algorithm 1, certified at its improvement steps.
 
 Notation: the paper's batch size ``m`` is called ``b`` here, because ``m`` is
 the number of actions; the paper's cost-to-go ``J`` is ``V`` and its discount

@@ -151,3 +151,96 @@ def test_planted_mistakes_are_caught():
     V_early, _, _ = certified_correction(mdp, V0, 10, 4, eps=1e-30, max_sweeps=st.sweeps - 1)
     assert trace[-2][1] > 1e-8
     assert np.max(np.abs(V_early - Vs)) > np.max(np.abs(V - Vs))
+
+
+# ---- the same correction by Algorithm 1 (certified at improvement steps)
+
+from oracle.refine import certified_correction_mpi  # noqa: E402
+
+
+def loop_greedy(mdp, V):
+    """(residual max|TV - V|, lowest minimising action per state), plain loops."""
+    worst, pol = 0.0, np.zeros(mdp.n, dtype=np.int64)
+    for s in range(mdp.n):
+        best, arg = float("inf"), 0
+        for a in range(mdp.m):
+            q = float(mdp.c[s, a]) + mdp.gamma * sum(
+                float(mdp.P[s, a, j]) * float(V[j]) for j in range(mdp.n))
+            if q < best:
+                best, arg = q, a
+        pol[s] = arg
+        worst = max(worst, abs(best - float(V[s])))
+    return worst, pol
+
+
+@pytest.mark.parametrize("n,m,seed", [(4, 2, 1), (5, 3, 2), (6, 2, 3)])
+@pytest.mark.parametrize("K,b", [(1, 1), (3, 2), (5, 6)])
+def test_mpi_bounds_hold_against_brute_force(n, m, seed, K, b):
+    b = min(b, n)
+    mdp = dense_random(n, m, seed, gamma=0.95)
+    Vs, _ = brute_force_optimum(mdp)
+    V0 = Vs + np.random.default_rng(seed).uniform(-0.3, 0.3, n)
+    trace = []
+    V, pol, st = certified_correction_mpi(mdp, V0, K, b, 7, eps=1e-7, trace=trace)
+    assert st.converged and st.bound_out <= 1e-7
+    assert np.max(np.abs(V - Vs)) <= st.bound_out + 1e-12
+    assert len(trace) == st.outer_iters + 1 and st.sweeps == K * st.outer_iters
+    # the residuals are those of plain loops, and the returned policy is greedy
+    res, lp = loop_greedy(mdp, V)
+    assert abs(res - st.residual_out) <= 1e-13
+    assert np.array_equal(lp, pol)
+    assert abs(loop_greedy(mdp, V0)[0] - st.residual_in) <= 1e-13
+
+
+def test_mpi_replays_algorithm_1():
+    """Improvement (greedy at V, plain loops), then K sweeps of B_{mu,b} with
+    that policy; the stop is the first improvement whose certificate is <= eps."""
+    mdp = dense_random(12, 3, 4, gamma=0.9)
+    Vs, _, _ = policy_iteration(mdp)
+    V0 = Vs + np.random.default_rng(3).uniform(-0.05, 0.05, 12)
+    K, b, seed, eps = 2, 5, 9, 1e-8
+    trace = []
+    V, _, st = certified_correction_mpi(mdp, V0, K, b, seed, eps, first_sweep=4, trace=trace)
+    Vt, t = V0.copy(), 4
+    for i, (res, bound) in enumerate(trace):
+        r, mu = loop_greedy(mdp, Vt)
+        assert abs(r - res) <= 1e-13 and bound == res / (1 - mdp.gamma)
+        assert (bound <= eps) == (i == len(trace) - 1)
+        if i == len(trace) - 1:
+            break
+        for _ in range(K):
+            Vt, _, _ = oracle.mb_sweep(mdp, Vt, b, sweep_permutation(12, seed, t), policy=mu)
+            t += 1
+    assert np.array_equal(V, Vt)
+    assert np.max(np.abs(V - Vs)) <= eps
+
+
+def test_mpi_measurement_mode_and_final_certificate():
+    mdp = dense_random(20, 3, 6, gamma=0.9)
+    Vs, _, _ = policy_iteration(mdp)
+    V, _, st = certified_correction_mpi(mdp, np.zeros(20), 3, 4, 2, eps=1e-6, V_ref=Vs)
+    assert st.converged and st.final_err_ref <= 1e-6
+    assert st.final_err_ref == float(np.max(np.abs(V - Vs)))
+    # the output's certificate comes from an improvement step at the output itself
+    assert abs(loop_greedy(mdp, V)[0] - st.residual_out) <= 1e-13
+    assert np.max(np.abs(V - Vs)) <= st.bound_out + 1e-12
+
+
+def test_mpi_planted_mistake_evaluation_changes_certify_nothing():
+    """Certifying with the evaluation sweeps' changes (as the VI form may)
+    would stop at J_mu of a suboptimal policy: the changes vanish while the
+    error does not."""
+    mdp = dense_random(8, 3, 12, gamma=0.9)
+    Vs, _ = brute_force_optimum(mdp)
+    # a start whose greedy policy is not optimal
+    V0 = np.zeros(8)
+    _, mu0 = loop_greedy(mdp, V0)
+    Q = oracle.q_values(mdp, np.arange(8), Vs)
+    assert np.any(Q[np.arange(8), mu0] > Q.min(axis=1) + 1e-9)
+    V = V0.copy()
+    for t in range(300):
+        V, _, dv = oracle.mb_sweep(mdp, V, 3, sweep_permutation(8, 1, t), policy=mu0)
+    assert mdp.gamma * dv / (1 - mdp.gamma) <= 1e-9      # the wrong certificate fires
+    assert np.max(np.abs(V - Vs)) > 1e-3                 # but V is far from J*
+    _, _, st = certified_correction_mpi(mdp, V0, 300, 3, 1, eps=1e-9)
+    assert st.outer_iters >= 1 and st.converged          # the right one goes on improving
