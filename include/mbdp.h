@@ -373,6 +373,55 @@ mbdp_status mpi_solve(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy,
                       int64_t max_outer, void* workspace, size_t ws_bytes, hipStream_t stream,
                       mbdp_stats* stats);
 
+/* Certified FP64 correction (an extension: the paper fixes no precision).
+ * Typical use: V is the solution of a reduced-precision copy of this MDP
+ * (mdp_create_dense_q / mdp_create_csr_q), which differs from this MDP's J*
+ * by the storage error; the correction brings it to within eps of this
+ * MDP's J*, with a certificate.  Everything is FP64 on the GPU: V, the
+ * accumulation of every dot product with the handle's FP32 transition
+ * values (widened exactly), costs, minima and tests.
+ * The certificate is the contraction property (Sec. III-B): every B_{sigma,b}
+ * of eq. (11), like T of eq. (7), is a gamma-contraction in the max norm
+ * with fixed point J*, so max|V - J*| <= max|TV - V| / (1 - gamma), and a
+ * sweep V' = B V gives max|V' - J*| <= min(gamma max|V' - V| / (1 - gamma),
+ * gamma max|V - J*|) (bounds of exact arithmetic).
+ * Steps: one pass of eq. (7) over all states at the input gives its residual
+ * max|TV - V|.  Then
+ *   K = 0:  sweeps t = first_sweep, first_sweep + 1, ... of B_{sigma_t,b}
+ *           until the chained bound above is <= eps (max_iters sweeps at
+ *           most);
+ *   K >= 1: Algorithm 1: K sweeps of B_{mu,sigma_t,b} with mu the greedy
+ *           policy of the last improvement step, then the improvement step
+ *           (a pass of eq. (7), V fixed), until an improvement step's
+ *           residual / (1 - gamma) is <= eps (max_iters improvement steps
+ *           at most).
+ * The input itself is returned unchanged when its residual certifies eps.
+ * With V_ref (device FP64[n]) the stop is instead the first V (the input or
+ * a sweep's result) with max|V - V_ref| <= eps (measurement mode).
+ * V: device FP64[n], in and out.  policy_out: device int32[n], the greedy
+ * policy at the output (lowest index on ties), or NULL.  The handle must
+ * hold FP32 values (MBDP_ERR_UNSUPPORTED otherwise); the workspace is that
+ * of mdp_workspace_bytes(h, b).  Synchronises `stream`.  Returns
+ * MBDP_ERR_NOT_CONVERGED (soft) when the limit was reached. */
+typedef struct {
+  double residual_in;   /* max|TV - V| at the input */
+  double residual_out;  /* max|TV - V| at the output; NaN when not evaluated
+                           (K = 0 without policy_out after at least one sweep) */
+  double bound_out;     /* certified bound on max|V - J*| at the output:
+                           K = 0 the chained sweep bound, K >= 1 residual_out / (1 - gamma) */
+  double final_dv_inf;  /* max|V_t - V_{t-1}| of the last sweep (NaN if none) */
+  double final_err_ref; /* max|V - V_ref| at the output (NaN without V_ref) */
+  int64_t sweeps;       /* sweeps applied */
+  int64_t outer_iters;  /* K >= 1: improvement steps after the input's */
+  int32_t converged;    /* 1 if the stopping rule fired */
+  int32_t reserved;
+} mbdp_refine_stats;
+
+mbdp_status mdp_refine(mbdp_mdp_t h, double* V, int32_t* policy_out, int32_t K, int64_t b,
+                       uint64_t seed, uint64_t first_sweep, double eps, const double* V_ref,
+                       int64_t max_iters, void* workspace, size_t ws_bytes, hipStream_t stream,
+                       mbdp_refine_stats* stats);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* mbdp_last_error(void);
 

@@ -41,7 +41,7 @@ EXPORTS = [
     "mdp_set_tuning", "mdp_batch_workspace_bytes", "mdp_batch_upload", "mdp_batch_launch",
     "mdp_batch_read_stats", "mdp_multi_workspace_bytes", "mdp_multi_solve",
     "mdp_workspace_bytes", "mdp_engine", "mdp_validate", "mbdp_permutation", "mb_sweep",
-    "mbdp_sync_status", "vi_solve", "mpi_solve", "mbdp_last_error",
+    "mbdp_sync_status", "vi_solve", "mpi_solve", "mdp_refine", "mbdp_last_error",
 ]
 
 
@@ -60,6 +60,17 @@ class Stats(ctypes.Structure):
                 ("policy_changes_last", ctypes.c_int64), ("recentrings", ctypes.c_int64),
                 ("final_dv_inf", ctypes.c_double), ("final_err_ref", ctypes.c_double),
                 ("converged", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class RefineStats(ctypes.Structure):
+    _fields_ = [("residual_in", ctypes.c_double), ("residual_out", ctypes.c_double),
+                ("bound_out", ctypes.c_double), ("final_dv_inf", ctypes.c_double),
+                ("final_err_ref", ctypes.c_double), ("sweeps", ctypes.c_int64),
+                ("outer_iters", ctypes.c_int64), ("converged", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
@@ -138,6 +149,8 @@ _SIGS = {
                         ctypes.c_size_t, _P, ctypes.POINTER(Stats)]),
     "mpi_solve": (_I32, [_P, _P, _P, _P, _I32, _I32, _I64, _U64, _U64, _D, _D, _P, _I64, _P,
                          ctypes.c_size_t, _P, ctypes.POINTER(Stats)]),
+    "mdp_refine": (_I32, [_P, _P, _P, _I32, _I64, _U64, _U64, _D, _P, _I64, _P,
+                          ctypes.c_size_t, _P, ctypes.POINTER(RefineStats)]),
     "mbdp_last_error": (ctypes.c_char_p, []),
 }
 
@@ -496,6 +509,27 @@ def mpi_solve(h, V, policy, K, b, seed, ws, policy_is_init=True, first_sweep=0, 
                              int(K), int(b), int(seed), int(first_sweep), float(tol_dv),
                              float(eps), _ptr(V_ref), int(max_outer), _ptr(ws), ws.numel(),
                              _stream(stream), ctypes.byref(st))
+    if status != MBDP_ERR_NOT_CONVERGED:
+        _check(status)
+    return st.as_dict()
+
+
+def mdp_refine(h, V, b, seed, ws, K=0, eps=1e-6, V_ref=None, first_sweep=0, max_iters=100000,
+               policy_out=None, stream=None):
+    """Certified FP64 correction of V (FP64, in place) on an FP32 handle.
+
+    Returns the statistics dict (``converged`` False when the limit was hit).
+    """
+    import torch
+    _require(V, torch.float64, h.n, "V")
+    if V_ref is not None:
+        _require(V_ref, torch.float64, h.n, "V_ref")
+    if policy_out is not None:
+        _require(policy_out, torch.int32, h.n, "policy_out")
+    st = RefineStats()
+    status = lib().mdp_refine(h.ptr, _ptr(V), _ptr(policy_out), int(K), int(b), int(seed),
+                              int(first_sweep), float(eps), _ptr(V_ref), int(max_iters),
+                              _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(st))
     if status != MBDP_ERR_NOT_CONVERGED:
         _check(status)
     return st.as_dict()

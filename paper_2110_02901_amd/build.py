@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libmbdp.so")
 OBJDIR = os.path.join(HERE, "_build")
 # one translation unit per kernel family, compiled in parallel
 SOURCES = ["mbdp_kernels.hip", "mbdp_kernels_lp_dense.hip", "mbdp_kernels_lp_ell.hip", "mbdp_batch.hip", "mbdp_multi.hip",
-           "mbdp_kernels_lp_band.hip", "mbdp_runtime.hip"]
+           "mbdp_kernels_lp_band.hip", "mbdp_refine.hip", "mbdp_runtime.hip"]
 
 COMPILE_FLAGS = [
     "--offload-arch=gfx950",

@@ -168,10 +168,12 @@ __device__ __forceinline__ double slot_double(Control* ctl, int slot, int i) {
 
 // ------------------------------------------------------------ per-state commit
 
-struct Ctx {
-  float* rd;   // read buffer: W before the current batch (complete)
-  float* wr;   // write buffer
+template <class VT>
+struct CtxT {
+  VT* rd;   // read buffer: W before the current batch (complete)
+  VT* wr;   // write buffer
 };
+using Ctx = CtxT<float>;
 
 // Costs of a row: the solvers always read the FP64 shifted costs (equal to
 // c until the first re-centring), a single sweep reads c itself.  The
@@ -1187,13 +1189,15 @@ struct CsrEngine {
 
 // ------------------------------------------------------------ the persistent kernel
 
-template <class Acc>
+// VT is the type of the value buffers: float for the solvers (W = V - R),
+// double for the FP64 correction (V itself).
+template <class Acc, class VT = float>
 struct Driver {
   const KParams& p;
   GridBarrier g;
   Acc L;
-  float* buf0;
-  float* buf1;
+  VT* buf0;
+  VT* buf1;
   int64_t phase;          // batches processed (parity selects the read buffer)
   const int32_t* prev_order;
   int64_t prev_count;     // states of the previous batch still to copy forward
@@ -1209,8 +1213,13 @@ struct Driver {
     g.nblocks = gridDim.x;
     g.timeout = p.timeout_ticks;
     L.init();
-    buf0 = p.vbuf0;
-    buf1 = p.vbuf1;
+    if constexpr (sizeof(VT) == sizeof(double)) {
+      buf0 = p.vd0;
+      buf1 = p.vd1;
+    } else {
+      buf0 = p.vbuf0;
+      buf1 = p.vbuf1;
+    }
     phase = 0;
     prev_order = nullptr;
     prev_count = 0;
@@ -1255,8 +1264,8 @@ struct Driver {
   }
 
   // buffer holding V before the current batch (complete) / the other one
-  __device__ __forceinline__ float* rd_buf() const { return (phase & 1) ? buf1 : buf0; }
-  __device__ __forceinline__ float* wr_buf() const { return (phase & 1) ? buf0 : buf1; }
+  __device__ __forceinline__ VT* rd_buf() const { return (phase & 1) ? buf1 : buf0; }
+  __device__ __forceinline__ VT* wr_buf() const { return (phase & 1) ? buf0 : buf1; }
 
   __device__ __forceinline__ int slot() const { return (int)(epoch % 3); }
 
@@ -1268,7 +1277,7 @@ struct Driver {
     const int32_t* ord = p.order + (size_t)(t % 3) * (size_t)n;
     for (int64_t k = 0; k < nb; ++k) {
       const int64_t kb = k * b, bk = min(b, n - kb);
-      Ctx c{rd_buf(), wr_buf()};
+      CtxT<VT> c{rd_buf(), wr_buf()};
       // copy the previous batch forward, except states this batch rewrites
       // (only possible for the first batch, whose states are stamped)
       const uint32_t st = stamp(t);
@@ -1349,7 +1358,7 @@ struct Driver {
   __device__ __forceinline__ bool improve(bool count) {
     if constexpr (Eng::kBand) return improve_band<Eng, CE>(count);
     if (blockIdx.x == 0 && threadIdx.x == 0) reset_slot(p.ctl, (int)((epoch + 1) % 3));
-    Ctx c{rd_buf(), wr_buf()};
+    CtxT<VT> c{rd_buf(), wr_buf()};
     Eng::template batch<CE, true>(p, nullptr, p.n, c, count ? kModeImproveCount : kModeImprove, L);
     L.flush(p.ctl, slot());
     if (!grid_sync(g)) return false;

@@ -10,7 +10,7 @@ namespace mbdp {
 enum Storage : int32_t { kDense = 0, kEll = 1, kCsr = 2 };
 // Storage of transition probabilities (values of mbdp_dtype in include/mbdp.h).
 enum ValueType : int32_t { kF32 = 0, kBF16 = 1, kFP8 = 2 };
-enum Task : int32_t { kTaskSweep = 0, kTaskVI = 1, kTaskMPI = 2 };
+enum Task : int32_t { kTaskSweep = 0, kTaskVI = 1, kTaskMPI = 2, kTaskRefine = 3 };
 
 // Device-side error codes recorded in Control::error.
 enum DeviceError : uint32_t {
@@ -52,6 +52,10 @@ struct alignas(256) Control {
   int converged;
   int pad2;
   float dv_last;                 // last sweep's max |dV| as FP32 (mb_sweep)
+  float pad3;
+  double residual_in;            // FP64 correction: max |TV - V| of the input
+  double residual_out;           // FP64 correction: max |TV - V| of the output (NaN: not evaluated)
+  double bound_out;              // FP64 correction: certified bound on max |V - J*|
   unsigned long long bar_slots[kMaxBlocks] __attribute__((aligned(256)));  // arrival generations
 };
 
@@ -79,6 +83,8 @@ struct KParams {
   // vectors
   float* vbuf0;            // caller's V
   float* vbuf1;            // ping-pong partner, workspace
+  double* vd0;             // FP64 correction: caller's V
+  double* vd1;             // FP64 correction: ping-pong partner, workspace
   int32_t* policy;         // B_{mu,b} policy in; improvement out
   int32_t* argmin_out;
   const int32_t* perm;     // explicit order or null
@@ -156,6 +162,9 @@ enum Engine : int { kEngineDense = 0, kEngineEll = 1, kEngineBand = 2, kEngineCs
 // Fills p.splits from the grid actually used and launches the persistent
 // kernel cooperatively.  Returns 0 or -1 with a message in err.
 int launch_solve(KParams p, LaunchShape shape, void* stream, char* err, size_t errlen);
+// The FP64 correction kernel (mbdp_refine.hip) for an FP32 handle; the same
+// contract as launch_solve.
+int launch_refine(KParams p, LaunchShape shape, void* stream, char* err, size_t errlen);
 // The kernel family launch_solve would run for p (no device work).
 int query_engine(const KParams& p, LaunchShape shape, int* engine, char* err, size_t errlen);
 int launch_zero(void* ptr, size_t bytes, void* stream);

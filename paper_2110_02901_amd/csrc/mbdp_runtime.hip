@@ -963,4 +963,61 @@ mbdp_status mpi_solve(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy,
   return MBDP_OK;
 }
 
+mbdp_status mdp_refine(mbdp_mdp_t h, double* V, int32_t* policy_out, int32_t K, int64_t b,
+                       uint64_t seed, uint64_t first_sweep, double eps, const double* V_ref,
+                       int64_t max_iters, void* workspace, size_t ws_bytes, hipStream_t stream,
+                       mbdp_refine_stats* stats) {
+  if (!h) return fail(MBDP_ERR_INVALID_ARG, "handle is NULL");
+  if (!V) return fail(MBDP_ERR_INVALID_ARG, "V is NULL");
+  if (h->vdtype != kF32)
+    return fail(MBDP_ERR_UNSUPPORTED, "the FP64 correction needs a handle with FP32 values");
+  if (K < 0) return fail(MBDP_ERR_INVALID_ARG, "K = %d < 0", K);
+  if (b < 1 || b > h->n)
+    return fail(MBDP_ERR_INVALID_ARG, "batch size b = %lld not in [1, n = %lld]", (long long)b,
+                (long long)h->n);
+  if (max_iters < 0) return fail(MBDP_ERR_INVALID_ARG, "max_iters must be >= 0");
+  if (!(eps >= 0.0)) return fail(MBDP_ERR_INVALID_ARG, "eps must be >= 0");
+  mbdp_status st = check_ws(h, workspace, ws_bytes);
+  if (st != MBDP_OK) return st;
+  const WsLayout w = layout(h);
+  char* base = static_cast<char*>(workspace);
+  KParams p = base_params(h, workspace, nullptr, b);
+  p.task = kTaskRefine;
+  p.vd0 = V;
+  p.vd1 = reinterpret_cast<double*>(base + w.shift);  // n doubles
+  // Algorithm 1 needs a policy: the caller's, or n words of the workspace
+  p.policy = policy_out ? policy_out
+                        : (K > 0 ? reinterpret_cast<int32_t*>(base + w.vbuf1) : nullptr);
+  p.K = K;
+  p.seed = seed;
+  p.first_sweep = first_sweep;
+  p.eps = eps;
+  p.vref = V_ref;
+  p.max_sweeps = max_iters;
+  p.max_outer = max_iters;
+  if (launch_zero(workspace, w.zero_bytes, stream) != 0)
+    return fail(MBDP_ERR_HIP, "workspace clear failed: %s", hipGetErrorString(hipGetLastError()));
+  char err[256] = {0};
+  if (launch_refine(p, shape_of(h), stream, err, sizeof err) != 0)
+    return fail(MBDP_ERR_HIP, "%s", err);
+  Control c;
+  st = finish(workspace, stream, &c);
+  if (st != MBDP_OK) return st;
+  if (stats) {
+    stats->residual_in = c.residual_in;
+    stats->residual_out = c.residual_out;
+    stats->bound_out = c.bound_out;
+    stats->final_dv_inf = c.final_dv_inf;
+    stats->final_err_ref = V_ref ? c.final_err_ref : NAN;
+    stats->sweeps = c.sweeps;
+    stats->outer_iters = c.outer_iters;
+    stats->converged = c.converged;
+    stats->reserved = 0;
+  }
+  if (!c.converged)
+    return fail(MBDP_ERR_NOT_CONVERGED, "eps not reached within %lld %s", (long long)max_iters,
+                K > 0 ? "outer iterations" : "sweeps");
+  return MBDP_OK;
+}
+
 }  // extern "C"
