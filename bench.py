@@ -80,29 +80,89 @@ def committed_traffic(workload, b, sweeps_per_launch):
     return sweeps_per_launch * per_sweep + prologue
 
 
-def cpu_baseline(mdp, wl_name, b, seed, budget_s=20.0):
-    """The FP64 oracle's sweeps on the same MDP, timed on the host: whole
-    sweeps from V = 0 until the budget is spent (at least one)."""
-    import oracle
+def host_info():
+    """The host the CPU baseline runs on: logical CPUs, CPU model, BLAS threads."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = 1
     try:
         from threadpoolctl import threadpool_info
-        cores = max((t.get("num_threads", 1) for t in threadpool_info()), default=1)
+        blas = max((t.get("num_threads", 1) for t in threadpool_info()), default=1)
     except Exception:
-        cores = 1
-    n, m = mdp.n, mdp.m
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model, "blas_threads": int(blas)}
+
+
+def _oracle_sweep_rate(mdp, b, seed, budget_s, threads=None):
+    """Whole FP64 oracle sweeps of B_b from V = 0 until the budget is spent
+    (at least one): (sweeps, seconds)."""
+    import oracle
+    from contextlib import nullcontext
+    try:
+        from threadpoolctl import threadpool_limits
+        ctx = threadpool_limits(threads) if threads else nullcontext()
+    except Exception:
+        ctx = nullcontext()
+    n = mdp.n
     V = np.zeros(n)
     sweeps = 0
+    with ctx:
+        t0 = time.perf_counter()
+        while True:
+            V, _, _ = oracle.mb_sweep(mdp, V, b, oracle.sweep_permutation(n, seed, sweeps))
+            sweeps += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        dt = time.perf_counter() - t0
+    return sweeps, dt
+
+
+def _oracle_small_time_to_eps(eps):
+    """The oracle's MB-VI on the 64-state workload (its J* by policy
+    iteration, untimed), timed from V = 0 to the first sweep with
+    max|V - J*| <= eps: the whole time to eps, where the oracle finishes."""
+    import oracle
+    from paper_2110_02901_amd import inputs
+    wl = inputs.WORKLOADS["dense-64x4"]
+    P, c = inputs.dense_mdp(wl["n"], wl["m"], wl["alpha"], wl["data_seed"], dtype=np.float32)
+    mdp = oracle.DenseMDP(P, c, wl["gamma"])
+    Vs, _, _ = oracle.policy_iteration(mdp)
+    b = wl["batch_sizes"][0]
     t0 = time.perf_counter()
-    while True:
-        V, _, _ = oracle.mb_sweep(mdp, V, b, oracle.sweep_permutation(n, seed, sweeps))
-        sweeps += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": sweeps * n * m / dt, "unit": "backups/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": "%d FP64 sweeps of B_b (b=%d) on the full %s MDP (n=%d, m=%d) from V=0, "
-                      "%.1f s" % (sweeps, b, wl_name, n, m, dt)}
+    _, _, st = oracle.value_iteration(mdp, b, wl["perm_seed"], tol_dv=-1.0, V_ref=Vs, eps=eps)
+    return {"workload": "dense-64x4", "b": b, "sweeps": st.sweeps,
+            "seconds": time.perf_counter() - t0}
+
+
+def cpu_baseline(mdp, wl_name, b, seed, budget_s=20.0, gpu_sweeps=None, eps=1e-6):
+    """The FP64 oracle on the same MDP, timed on the host with every BLAS
+    thread and with one thread (half the budget each), plus the oracle's time
+    to eps on the 64-state workload and, for this workload, the measured
+    sweep time times the GPU's sweep count (an extrapolation)."""
+    host = host_info()
+    n, m = mdp.n, mdp.m
+    sw_all, dt_all = _oracle_sweep_rate(mdp, b, seed, budget_s / 2)
+    sw_one, dt_one = _oracle_sweep_rate(mdp, b, seed, budget_s / 2, threads=1)
+    out = {"value": sw_all * n * m / dt_all, "unit": "backups/s", "cores": host["blas_threads"],
+           "kind": "oracle",
+           "sample": "%d FP64 sweeps of B_b (b=%d) on the full %s MDP (n=%d, m=%d) from V=0 "
+                     "in %.1f s with %d BLAS threads; %d sweeps in %.1f s with one"
+                     % (sw_all, b, wl_name, n, m, dt_all, host["blas_threads"], sw_one, dt_one),
+           "one_thread_value": sw_one * n * m / dt_one,
+           "host": host,
+           "small_time_to_eps": _oracle_small_time_to_eps(eps)}
+    if gpu_sweeps:
+        out["time_to_eps_extrapolated_s"] = {
+            "sweeps": gpu_sweeps, "all_threads": gpu_sweeps * dt_all / sw_all,
+            "one_thread": gpu_sweeps * dt_one / sw_one,
+            "note": "the GPU's sweep count to eps times the oracle's measured time per sweep"}
+    return out
 
 
 def run_multi(args, dev):
@@ -254,6 +314,7 @@ def run_batch(args, dev):
     t0 = time.perf_counter()
     items = []
     total_bytes = 0
+    padded_bytes = 0
     for i in range(count):
         n = int(ns[i])
         ld = (n + 63) // 64 * 64  # rows of whole 128-byte lines
@@ -269,7 +330,8 @@ def run_batch(args, dev):
                       "b": (n + 7) // 8, "seed": 2000 + i,
                       "V": torch.zeros(n, dtype=torch.float64, device=dev), "policy": None,
                       "lanes": 0})
-        total_bytes += n * m * (2 * ld + 8)
+        total_bytes += n * m * (2 * n + 8)  # the method's bytes: row, scale, cost
+        padded_bytes += n * m * (2 * ld + 8)
     torch.cuda.synchronize()
     log("generated %d MDPs (%.1f GB of BF16 rows) in %.1f s"
         % (count, total_bytes / 1e9, time.perf_counter() - t0))
@@ -289,7 +351,8 @@ def run_batch(args, dev):
     if args.profile_sweeps:
         # counter runs: two eager launches of exactly S and 3S sweeps of every MDP
         out = {"workload": "batch-512", "launches": [], "sources_hash": sources_hash("batch"),
-               "algorithmic_bytes_per_sweep": float(total_bytes)}
+               "algorithmic_bytes_per_sweep": float(total_bytes),
+               "padded_bytes_per_sweep": float(padded_bytes)}
         for sweeps in (args.profile_sweeps, 3 * args.profile_sweeps):
             for it in items:
                 it["V"].zero_()
@@ -335,15 +398,20 @@ def run_batch(args, dev):
     if not all(st["converged"] for st in stats):
         raise RuntimeError("batch did not converge")
     backups = sum(st["sweeps"] * int(ns[i]) * m for i, st in enumerate(stats))
-    bytes_step = sum(st["sweeps"] * int(ns[i]) * m * (2 * items[i]["ld"] + 8)
+    bytes_step = sum(st["sweeps"] * int(ns[i]) * m * (2 * int(ns[i]) + 8)
                      for i, st in enumerate(stats))
+    bytes_padded = sum(st["sweeps"] * int(ns[i]) * m * (2 * items[i]["ld"] + 8)
+                       for i, st in enumerate(stats))
     gbps = bytes_step * args.steps / kernel_s / 1e9
     traffic = None
     vals = _traffic_file("batch-512")
     if vals.get("sources_hash") == sources_hash("batch"):
         try:
-            traffic = (float(vals["hbm_bytes_per_sweep"]) / float(vals["algorithmic_bytes_per_sweep"])
-                       * bytes_step + float(vals["hbm_bytes_prologue"]))
+            # counters per padded byte moved (rows of whole 128-byte lines), scaled
+            # to this solve's padded bytes
+            per = float(vals.get("padded_bytes_per_sweep", vals["algorithmic_bytes_per_sweep"]))
+            traffic = (float(vals["hbm_bytes_per_sweep"]) / per * bytes_padded
+                       + float(vals["hbm_bytes_prologue"]))
         except (KeyError, ValueError):
             traffic = None
     sweeps = [st["sweeps"] for st in stats]
@@ -410,7 +478,8 @@ def run_batch(args, dev):
         "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": gbps / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": "batch_kernel (a workgroup or a team per MDP)",
-                     "algorithmic_bytes_per_backup": "2 ld + 8"},
+                     "algorithmic_bytes_per_backup": "2 n + 8",
+                     "padding_overhead": bytes_padded / bytes_step},
     }
     print(json.dumps(line), flush=True)
 
@@ -623,47 +692,73 @@ def main():
 
     precision = None
     if h32 is not h:
-        # the stored MDP's solution as a warm start for FP32 sweeps to eps of
-        # the FP32 MDP: the time the reduced precision saves at equal accuracy
-        V.zero_()
+        # The stored MDP's solve stops once its own certified distance to
+        # J*(stored), gamma dV / (1 - gamma), is below the storage error
+        # (measured above, untimed): sweeping further cannot bring V closer
+        # to the FP32 MDP's J*.  The FP64 correction (mdp_refine, on the FP32
+        # handle) then takes V to eps of J*(FP32): certified (its own stop
+        # rule, no reference), by sweeps (K = 0) or by Algorithm 1 (K = 5),
+        # and in measurement mode (first crossing of eps against the FP32
+        # reference, the rule every other time here uses).
+        tol_stored = lp_err * (1.0 - gamma) / gamma
         V64 = torch.zeros(n, dtype=torch.float64, device=dev)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e2 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        s1 = mb.vi_solve(h, V, best_b, seed, ws, tol_dv=-1.0, eps=args.eps, V_ref=Vref,
-                         max_sweeps=20000, V64_out=V64)
-        e1.record(stream)
-        s2 = mb.vi_solve(h32, V, best_b, seed, ws, tol_dv=-1.0, eps=args.eps, V_ref=Vref32,
-                         max_sweeps=20000, first_sweep=s1["sweeps"])
-        e2.record(stream)
-        e2.synchronize()
-        V.zero_()
-        s3 = mb.vi_solve(h32, V, best_b, seed, ws, tol_dv=-1.0, eps=args.eps, V_ref=Vref32,
-                         max_sweeps=20000)
-        torch.cuda.synchronize()
-        t_f32 = None
+
+        def lp_run(K, certified):
+            V.zero_()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e2 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            s1 = mb.vi_solve(h, V, best_b, seed, ws, tol_dv=tol_stored, max_sweeps=20000,
+                             V64_out=V64)
+            e1.record(stream)
+            s2 = mb.mdp_refine(h32, V64, best_b, seed, ws, K=K, eps=args.eps,
+                               V_ref=None if certified else Vref32, first_sweep=s1["sweeps"],
+                               max_iters=20000)
+            e2.record(stream)
+            e2.synchronize()
+            err = float((V64 - Vref32).abs().max())
+            out = {"stored_solve": {"sweeps": s1["sweeps"], "ms": e0.elapsed_time(e1)},
+                   "fp64_correction": {"K": K, "sweeps": s2["sweeps"],
+                                       "improvements": s2["outer_iters"],
+                                       "residual_in": s2["residual_in"],
+                                       "residual_out": s2["residual_out"],
+                                       "certified_bound": s2["bound_out"],
+                                       "ms": e1.elapsed_time(e2),
+                                       "converged": bool(s2["converged"])},
+                   "total_ms": e0.elapsed_time(e2),
+                   "err_vs_f32_reference": err}
+            log("%s + FP64 correction K=%d (%s): stored %d sweeps %.1f ms, correction %d "
+                "sweeps %d improvements %.1f ms (residual in %.3g, bound %.3g), total %.1f ms, "
+                "max|V - J*(FP32)| = %.3g"
+                % (args.precision, K, "certified" if certified else "to eps of the reference",
+                   s1["sweeps"], e0.elapsed_time(e1), s2["sweeps"], s2["outer_iters"],
+                   e1.elapsed_time(e2), s2["residual_in"], s2["bound_out"], e0.elapsed_time(e2),
+                   err))
+            return out
+
+        runs = {}
+        for K, certified in ((0, True), (5, True), (0, False), (5, False)):
+            lp_run(K, certified)  # warm-up
+            runs["k%d_%s" % (K, "certified" if certified else "measured")] = lp_run(K, certified)
         e3 = torch.cuda.Event(enable_timing=True)
         e4 = torch.cuda.Event(enable_timing=True)
         V.zero_()
         e3.record(stream)
-        mb.vi_solve(h32, V, best_b, seed, ws, tol_dv=-1.0, eps=args.eps, V_ref=Vref32,
-                    max_sweeps=20000)
+        s3 = mb.vi_solve(h32, V, best_b, seed, ws, tol_dv=-1.0, eps=args.eps, V_ref=Vref32,
+                         max_sweeps=20000)
         e4.record(stream)
         e4.synchronize()
         t_f32 = e3.elapsed_time(e4)
         precision = {
             "storage": args.precision,
             "err_stored_vs_f32_solution": lp_err,
-            "stored_solve": {"sweeps": s1["sweeps"], "ms": e0.elapsed_time(e1)},
-            "f32_finish_from_stored": {"sweeps": s2["sweeps"], "ms": e1.elapsed_time(e2),
-                                       "converged": bool(s2["converged"])},
-            "f32_alone": {"sweeps": s3["sweeps"], "ms": t_f32},
+            "stored_solve_tol_dv": tol_stored,
+            "stored_then_fp64_correction": runs,
+            "f32_alone": {"sweeps": s3["sweeps"], "ms": t_f32,
+                          "rule": "first sweep with max|V - J*(FP32)| <= eps"},
         }
-        log("%s: stored-MDP solve %d sweeps %.1f ms, FP32 finish %d sweeps %.1f ms; "
-            "FP32 alone %d sweeps %.1f ms" % (args.precision, s1["sweeps"], e0.elapsed_time(e1),
-                                              s2["sweeps"], e1.elapsed_time(e2), s3["sweeps"],
-                                              t_f32))
+        log("FP32 alone: %d sweeps %.1f ms" % (s3["sweeps"], t_f32))
 
     line = {
         "metric": METRIC,
@@ -712,7 +807,9 @@ def main():
         mdp = (oracle.DenseMDP(P, c, gamma) if dense
                else oracle.CsrMDP(rp, col, val, c, gamma))
         line["cpu_baseline"] = cpu_baseline(mdp, wl_name, best_b, seed,
-                                            args.cpu_baseline_seconds)
+                                            args.cpu_baseline_seconds,
+                                            gpu_sweeps=results[best_b][1]["sweeps"],
+                                            eps=args.eps)
     print(json.dumps(line), flush=True)
 
 

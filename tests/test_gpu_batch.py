@@ -290,7 +290,7 @@ def test_batch_512_full_size_sampled():
     items, host = [], {}
     for i in range(count):
         n = int(ns[i])
-        ld = (n + 15) // 16 * 16
+        ld = (n + 63) // 64 * 64  # rows of whole 128-byte lines, as the benchmark lays them out
         rows = torch.zeros(n * m, ld, dtype=torch.float32, device=dev())
         w = torch._standard_gamma(torch.ones(n * m, n, device=dev()), generator=gen)
         rows[:, :n] = w / w.sum(dim=1, keepdim=True)

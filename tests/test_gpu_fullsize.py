@@ -71,15 +71,18 @@ def test_dense_8192x16_vi_reaches_eps(c2, b):
     assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= out_tol(1e-6, Vstar)
 
 
-def test_dense_8192x16_mpi_reaches_eps(c2):
+@pytest.mark.parametrize("b", [256, 1024, 8192])
+def test_dense_8192x16_mpi_reaches_eps(c2, b):
     wl, h, mdp, Vstar = c2
-    ws = mb.workspace(h, 1024)
+    ws = mb.workspace(h, b)
     V = torch.zeros(wl["n"], dtype=torch.float32, device=dev())
+    V64 = torch.zeros(wl["n"], dtype=torch.float64, device=dev())
     pol = torch.zeros(wl["n"], dtype=torch.int32, device=dev())
-    st = mb.mpi_solve(h, V, pol, wl["K"], 1024, wl["perm_seed"], ws, policy_is_init=False,
-                      tol_dv=-1.0, eps=1e-6, V_ref=up(Vstar), max_outer=5000)
-    say("MPI K=5 b=1024: %s" % st)
+    st = mb.mpi_solve(h, V, pol, wl["K"], b, wl["perm_seed"], ws, policy_is_init=False,
+                      tol_dv=-1.0, eps=1e-6, V_ref=up(Vstar), max_outer=5000, V64_out=V64)
+    say("MPI K=5 b=%d: %s" % (b, st))
     assert st["converged"]
+    assert np.max(np.abs(V64.cpu().numpy() - Vstar)) <= 1e-6
     assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= out_tol(1e-6, Vstar)
 
 
@@ -158,26 +161,51 @@ def test_sparse_1M_lowprec_sweep(c3, dtype):
     run_sweep(h, mdp, V0, 65536, wl["perm_seed"], 0, check_arg=False)
 
 
-def test_sparse_1M_vi_certified_eps(c3):
-    """MB-VI at b = 65536 until max|dV| <= 1e-11, then the oracle's Bellman
-    residual of the FP64 iterate certifies the accuracy at full size:
-    max|V - J*| <= max|TV - V| / (1 - gamma) (contraction, Sec. III-B)."""
-    wl, h, mdp = c3
-    n = wl["n"]
-    ws = mb.workspace(h, 65536)
-    V = torch.zeros(n, dtype=torch.float32, device=dev())
-    V64 = torch.zeros(n, dtype=torch.float64, device=dev())
-    t0 = time.time()
-    st = mb.vi_solve(h, V, 65536, wl["perm_seed"], ws, tol_dv=1e-11, max_sweeps=20000,
-                     V64_out=V64)
-    say("VI to max|dV| <= 1e-11: %s in %.1f s" % (st, time.time() - t0))
-    assert st["converged"]
+def _certify(mdp, V64, gamma):
+    """The oracle's Bellman residual of the solve's FP64 iterate, which
+    certifies its accuracy at any size: max|V - J*| <= max|TV - V| / (1 -
+    gamma) (contraction, Sec. III-B)."""
     Vg = V64.cpu().numpy()
     TV, _ = oracle.greedy(mdp, Vg)
     resid = float(np.max(np.abs(TV - Vg)))
-    bound = resid / (1.0 - wl["gamma"])
+    bound = resid / (1.0 - gamma)
     say("oracle residual %.3g -> certified max|V - J*| <= %.3g" % (resid, bound))
-    assert bound <= 1e-6
+    return bound
+
+
+@pytest.mark.parametrize("b", [4096, 65536, 1_000_000])
+def test_sparse_1M_vi_certified_eps(c3, b):
+    """MB-VI at each benchmarked b until max|dV| <= 1e-11, certified by the
+    oracle's residual of the result."""
+    wl, h, mdp = c3
+    n = wl["n"]
+    ws = mb.workspace(h, b)
+    V = torch.zeros(n, dtype=torch.float32, device=dev())
+    V64 = torch.zeros(n, dtype=torch.float64, device=dev())
+    t0 = time.time()
+    st = mb.vi_solve(h, V, b, wl["perm_seed"], ws, tol_dv=1e-11, max_sweeps=30000,
+                     V64_out=V64)
+    say("VI b=%d to max|dV| <= 1e-11: %s in %.1f s" % (b, st, time.time() - t0))
+    assert st["converged"]
+    assert _certify(mdp, V64, wl["gamma"]) <= 1e-6
+
+
+def test_sparse_1M_mpi_certified_eps(c3):
+    """MB-MPI (K = 5) at b = 65536 until the policy is stable and the
+    residual of its improvement step is <= 1e-11, certified by the oracle's
+    residual of the result."""
+    wl, h, mdp = c3
+    n, b = wl["n"], 65536
+    ws = mb.workspace(h, b)
+    V = torch.zeros(n, dtype=torch.float32, device=dev())
+    V64 = torch.zeros(n, dtype=torch.float64, device=dev())
+    pol = torch.zeros(n, dtype=torch.int32, device=dev())
+    t0 = time.time()
+    st = mb.mpi_solve(h, V, pol, 5, b, wl["perm_seed"], ws, policy_is_init=False, tol_dv=1e-11,
+                      max_outer=10000, V64_out=V64)
+    say("MPI K=5 b=%d: %s in %.1f s" % (b, st, time.time() - t0))
+    assert st["converged"] and st["policy_changes_last"] == 0
+    assert _certify(mdp, V64, wl["gamma"]) <= 1e-6
 
 
 def test_sparse_50k_reaches_eps():

@@ -134,6 +134,36 @@ def test_fullsize_first_batch_sampled():
     assert np.all(np.isfinite(Vg))
 
 
+def test_fullsize_whole_sweep():
+    """n = 8192, m = 16, r = 32, BF16 rows, b = 1024: one sweep from a random
+    V0 against the oracle's whole multi-vector sweep of the stored MDP (its
+    own codes), so the states of later batches -- the last one included,
+    which reads the new values of all seven before it -- are checked too."""
+    n, m, r, b, gamma = 8192, 16, 32, 1024, 0.99
+    Pfull, c = inputs.dense_mdp(n, m, 0.1, 2, dtype=np.float32)
+    rows = up(Pfull.reshape(n * m, n))
+    q_gpu, s_gpu = mb.mdp_quantize_rows(rows, "bf16")
+    del rows
+    h = mb.mdp_create_dense_q(q_gpu.reshape(-1), "bf16", s_gpu, up(c), gamma)
+    C = inputs.multi_costs(n, m, r, 10, dtype=np.float32)
+    V0 = np.random.Generator(np.random.Philox(11)).uniform(5.0, 7.0, (n, r))
+    Vg, _, st = gpu_multi(h, C, V0, b, 3, max_sweeps=1, policy=False, first_sweep=4)
+    del h, q_gpu, s_gpu
+    q_ref, s_ref = qz.quantize_rows(Pfull.reshape(n * m, n), "bf16")
+    del Pfull
+    Pst = qz.dequantized(q_ref, s_ref, "bf16").reshape(n, m, n)
+    del q_ref
+    order = oracle.sweep_permutation(n, 3, 4)
+    ref, _, _ = om.multi_mb_sweep(Pst, C, gamma, V0, b, order)
+    bound = 2 * 2.0 ** -16 * float(np.max(np.abs(ref - V0))) + 1e-12
+    last = order[(n - 1) // b * b:]
+    err_all = float(np.max(np.abs(Vg - ref)))
+    err_last = float(np.max(np.abs(Vg[last] - ref[last])))
+    say("full size whole sweep: max err %.3g, last batch %.3g (bound %.3g)"
+        % (err_all, err_last, bound))
+    assert err_all <= bound
+
+
 def test_rejections():
     h, _, C = bf16_case(64, 2, 16, 0.9, 1)
     with pytest.raises(RuntimeError):
