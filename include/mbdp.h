@@ -356,6 +356,26 @@ mbdp_status vi_solve(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy_ou
                      const double* V_ref, int64_t max_sweeps, void* workspace, size_t ws_bytes,
                      hipStream_t stream, mbdp_stats* stats);
 
+/* vi_solve for callers that cannot allocate memory or pass a workspace
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same solve, the same arguments except the workspace,
+ * and the same results, bit for bit.  Its scratch memory is a file-scope
+ * device array of the library, 32 MiB on each device it runs on, held until
+ * the process ends; its address is looked up once per device (with that
+ * device current).  The call allocates nothing.  MDPs whose workspace
+ * (mdp_workspace_bytes) exceeds 32 MiB are rejected with
+ * MBDP_ERR_INVALID_ARG (dense n = 8192, m = 16 needs about 2.3 MB; sparse
+ * MDPs with k = 32, m = 8 up to about 300 000 states fit).  The handle's
+ * device must be current.  Every call on a device shares that device's
+ * array, which keeps the last call's contents (the control words are
+ * cleared at the start of each call): calls that overlap on one device --
+ * on different streams or from different threads -- race and must not be
+ * made.  Synchronises `stream`. */
+mbdp_status vi_solve_noalloc(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy_out,
+                             int64_t b, uint64_t seed, uint64_t first_sweep, double tol_dv,
+                             double eps, const double* V_ref, int64_t max_sweeps,
+                             hipStream_t stream, mbdp_stats* stats);
+
 /* MB-MPI: Algorithm 1 with its K policy-evaluation steps done by B_{mu,b}
  * (warm start from the current V).  policy (device int32[n]) is the initial
  * policy when policy_is_init != 0; otherwise the initial policy is the

@@ -41,7 +41,8 @@ EXPORTS = [
     "mdp_set_tuning", "mdp_batch_workspace_bytes", "mdp_batch_upload", "mdp_batch_launch",
     "mdp_batch_read_stats", "mdp_multi_workspace_bytes", "mdp_multi_solve",
     "mdp_workspace_bytes", "mdp_engine", "mdp_validate", "mbdp_permutation", "mb_sweep",
-    "mbdp_sync_status", "vi_solve", "mpi_solve", "mdp_refine", "mbdp_last_error",
+    "mbdp_sync_status", "vi_solve", "vi_solve_noalloc", "mpi_solve", "mdp_refine",
+    "mbdp_last_error",
 ]
 
 
@@ -149,6 +150,8 @@ _SIGS = {
                         ctypes.c_size_t, _P, ctypes.POINTER(Stats)]),
     "mpi_solve": (_I32, [_P, _P, _P, _P, _I32, _I32, _I64, _U64, _U64, _D, _D, _P, _I64, _P,
                          ctypes.c_size_t, _P, ctypes.POINTER(Stats)]),
+    "vi_solve_noalloc": (_I32, [_P, _P, _P, _P, _I64, _U64, _U64, _D, _D, _P, _I64, _P,
+                                ctypes.POINTER(Stats)]),
     "mdp_refine": (_I32, [_P, _P, _P, _I32, _I64, _U64, _U64, _D, _P, _I64, _P,
                           ctypes.c_size_t, _P, ctypes.POINTER(RefineStats)]),
     "mbdp_last_error": (ctypes.c_char_p, []),
@@ -490,6 +493,27 @@ def vi_solve(h, V, b, seed, ws, first_sweep=0, tol_dv=-1.0, eps=0.0, V_ref=None,
                             int(first_sweep), float(tol_dv), float(eps), _ptr(V_ref),
                             int(max_sweeps), _ptr(ws), ws.numel(), _stream(stream),
                             ctypes.byref(st))
+    if status != MBDP_ERR_NOT_CONVERGED:
+        _check(status)
+    return st.as_dict()
+
+
+def vi_solve_noalloc(h, V, b, seed, first_sweep=0, tol_dv=-1.0, eps=0.0, V_ref=None,
+                     max_sweeps=100000, policy_out=None, V64_out=None, stream=None):
+    """vi_solve without a workspace (the library's own scratch memory)."""
+    import torch
+    _require(V, torch.float32, h.n, "V")
+    if V_ref is not None:
+        _require(V_ref, torch.float64, h.n, "V_ref")
+    if policy_out is not None:
+        _require(policy_out, torch.int32, h.n, "policy_out")
+    if V64_out is not None:
+        _require(V64_out, torch.float64, h.n, "V64_out")
+    st = Stats()
+    status = lib().vi_solve_noalloc(h.ptr, _ptr(V), _ptr(V64_out), _ptr(policy_out), int(b),
+                                    int(seed), int(first_sweep), float(tol_dv), float(eps),
+                                    _ptr(V_ref), int(max_sweeps), _stream(stream),
+                                    ctypes.byref(st))
     if status != MBDP_ERR_NOT_CONVERGED:
         _check(status)
     return st.as_dict()

@@ -872,10 +872,14 @@ mbdp_status mbdp_sync_status(void* workspace, size_t ws_bytes, hipStream_t strea
   return finish(workspace, stream, &c);
 }
 
-mbdp_status vi_solve(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy_out, int64_t b,
-                     uint64_t seed, uint64_t first_sweep, double tol_dv, double eps,
-                     const double* V_ref, int64_t max_sweeps, void* workspace, size_t ws_bytes,
-                     hipStream_t stream, mbdp_stats* stats) {
+}  // extern "C"
+
+namespace {
+
+mbdp_status vi_solve_impl(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy_out,
+                          int64_t b, uint64_t seed, uint64_t first_sweep, double tol_dv,
+                          double eps, const double* V_ref, int64_t max_sweeps, void* workspace,
+                          size_t ws_bytes, hipStream_t stream, mbdp_stats* stats) {
   if (!h) return fail(MBDP_ERR_INVALID_ARG, "handle is NULL");
   if (!V) return fail(MBDP_ERR_INVALID_ARG, "V is NULL");
   if (b < 1 || b > h->n)
@@ -914,6 +918,71 @@ mbdp_status vi_solve(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy_ou
     return fail(MBDP_ERR_NOT_CONVERGED, "no stopping rule fired within %lld sweeps",
                 (long long)max_sweeps);
   return MBDP_OK;
+}
+
+// The no-allocation variant's scratch memory: a file-scope device array
+// (one copy per device, held until the process ends).  In host code its
+// name is only a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, looked up once per device with that device current.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// The current device's address of `scratch` (looked up on first use).
+mbdp_status scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(MBDP_ERR_UNSUPPORTED, "device %d is beyond the %d devices served", device,
+                kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(MBDP_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                  hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return MBDP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mbdp_status vi_solve(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy_out, int64_t b,
+                     uint64_t seed, uint64_t first_sweep, double tol_dv, double eps,
+                     const double* V_ref, int64_t max_sweeps, void* workspace, size_t ws_bytes,
+                     hipStream_t stream, mbdp_stats* stats) {
+  return vi_solve_impl(h, V, V64_out, policy_out, b, seed, first_sweep, tol_dv, eps, V_ref,
+                       max_sweeps, workspace, ws_bytes, stream, stats);
+}
+
+mbdp_status vi_solve_noalloc(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy_out,
+                             int64_t b, uint64_t seed, uint64_t first_sweep, double tol_dv,
+                             double eps, const double* V_ref, int64_t max_sweeps,
+                             hipStream_t stream, mbdp_stats* stats) {
+  if (!h) return fail(MBDP_ERR_INVALID_ARG, "handle is NULL");
+  const size_t need = layout(h).total;
+  if (need > kScratchBytes)
+    return fail(MBDP_ERR_INVALID_ARG,
+                "vi_solve_noalloc: this MDP needs %zu bytes of scratch memory, more than the "
+                "%zu bytes the library holds (use vi_solve with a workspace)",
+                need, kScratchBytes);
+  int device = -1;
+  MBDP_HIP(hipGetDevice(&device));
+  if (device != h->device)
+    return fail(MBDP_ERR_INVALID_ARG,
+                "vi_solve_noalloc: the current device (%d) is not the handle's (%d)", device,
+                h->device);
+  void* ws = nullptr;
+  const mbdp_status st = scratch_address(device, &ws);
+  if (st != MBDP_OK) return st;
+  return vi_solve_impl(h, V, V64_out, policy_out, b, seed, first_sweep, tol_dv, eps, V_ref,
+                       max_sweeps, ws, kScratchBytes, stream, stats);
 }
 
 mbdp_status mpi_solve(mbdp_mdp_t h, float* V, double* V64_out, int32_t* policy,
