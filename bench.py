@@ -114,13 +114,15 @@ def _oracle_sweep_rate(mdp, b, seed, budget_s, threads=None):
     sweeps = 0
     with ctx:
         t0 = time.perf_counter()
+        c0 = time.process_time()
         while True:
             V, _, _ = oracle.mb_sweep(mdp, V, b, oracle.sweep_permutation(n, seed, sweeps))
             sweeps += 1
             if time.perf_counter() - t0 >= budget_s:
                 break
         dt = time.perf_counter() - t0
-    return sweeps, dt
+        busy = time.process_time() - c0
+    return sweeps, dt, busy / dt
 
 
 def _oracle_small_time_to_eps(eps):
@@ -147,13 +149,17 @@ def cpu_baseline(mdp, wl_name, b, seed, budget_s=20.0, gpu_sweeps=None, eps=1e-6
     sweep time times the GPU's sweep count (an extrapolation)."""
     host = host_info()
     n, m = mdp.n, mdp.m
-    sw_all, dt_all = _oracle_sweep_rate(mdp, b, seed, budget_s / 2)
-    sw_one, dt_one = _oracle_sweep_rate(mdp, b, seed, budget_s / 2, threads=1)
-    out = {"value": sw_all * n * m / dt_all, "unit": "backups/s", "cores": host["blas_threads"],
+    sw_all, dt_all, used_all = _oracle_sweep_rate(mdp, b, seed, budget_s / 2)
+    sw_one, dt_one, _ = _oracle_sweep_rate(mdp, b, seed, budget_s / 2, threads=1)
+    # cores: the threads the run kept busy (process CPU time over wall time)
+    out = {"value": sw_all * n * m / dt_all, "unit": "backups/s",
+           "cores": max(1, int(round(used_all))), "cores_busy": used_all,
            "kind": "oracle",
            "sample": "%d FP64 sweeps of B_b (b=%d) on the full %s MDP (n=%d, m=%d) from V=0 "
-                     "in %.1f s with %d BLAS threads; %d sweeps in %.1f s with one"
-                     % (sw_all, b, wl_name, n, m, dt_all, host["blas_threads"], sw_one, dt_one),
+                     "in %.1f s with up to %d BLAS threads (%.1f busy on average); %d sweeps "
+                     "in %.1f s with one"
+                     % (sw_all, b, wl_name, n, m, dt_all, host["blas_threads"], used_all,
+                        sw_one, dt_one),
            "one_thread_value": sw_one * n * m / dt_one,
            "host": host,
            "small_time_to_eps": _oracle_small_time_to_eps(eps)}
@@ -703,14 +709,21 @@ def main():
         tol_stored = lp_err * (1.0 - gamma) / gamma
         V64 = torch.zeros(n, dtype=torch.float64, device=dev)
 
-        def lp_run(K, certified):
+        K_mpi = wl.get("K", 5)
+
+        def lp_run(stored, K, certified):
             V.zero_()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e2 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            s1 = mb.vi_solve(h, V, best_b, seed, ws, tol_dv=tol_stored, max_sweeps=20000,
-                             V64_out=V64)
+            if stored == "vi":
+                s1 = mb.vi_solve(h, V, best_b, seed, ws, tol_dv=tol_stored, max_sweeps=20000,
+                                 V64_out=V64)
+            else:  # residual <= (1 - gamma) err  =>  max|V - J*(stored)| <= err
+                pol.zero_()
+                s1 = mb.mpi_solve(h, V, pol, K_mpi, best_b, seed, ws, policy_is_init=False,
+                                  tol_dv=lp_err * (1.0 - gamma), max_outer=4000, V64_out=V64)
             e1.record(stream)
             s2 = mb.mdp_refine(h32, V64, best_b, seed, ws, K=K, eps=args.eps,
                                V_ref=None if certified else Vref32, first_sweep=s1["sweeps"],
@@ -718,7 +731,9 @@ def main():
             e2.record(stream)
             e2.synchronize()
             err = float((V64 - Vref32).abs().max())
-            out = {"stored_solve": {"sweeps": s1["sweeps"], "ms": e0.elapsed_time(e1)},
+            out = {"stored_solve": {"solver": stored, "sweeps": s1["sweeps"],
+                                    "improvements": s1["outer_iters"],
+                                    "ms": e0.elapsed_time(e1)},
                    "fp64_correction": {"K": K, "sweeps": s2["sweeps"],
                                        "improvements": s2["outer_iters"],
                                        "residual_in": s2["residual_in"],
@@ -728,37 +743,59 @@ def main():
                                        "converged": bool(s2["converged"])},
                    "total_ms": e0.elapsed_time(e2),
                    "err_vs_f32_reference": err}
-            log("%s + FP64 correction K=%d (%s): stored %d sweeps %.1f ms, correction %d "
+            log("%s %s + FP64 correction K=%d (%s): stored %d sweeps %.1f ms, correction %d "
                 "sweeps %d improvements %.1f ms (residual in %.3g, bound %.3g), total %.1f ms, "
                 "max|V - J*(FP32)| = %.3g"
-                % (args.precision, K, "certified" if certified else "to eps of the reference",
+                % (args.precision, stored, K,
+                   "certified" if certified else "to eps of the reference",
                    s1["sweeps"], e0.elapsed_time(e1), s2["sweeps"], s2["outer_iters"],
                    e1.elapsed_time(e2), s2["residual_in"], s2["bound_out"], e0.elapsed_time(e2),
                    err))
             return out
 
         runs = {}
-        for K, certified in ((0, True), (5, True), (0, False), (5, False)):
-            lp_run(K, certified)  # warm-up
-            runs["k%d_%s" % (K, "certified" if certified else "measured")] = lp_run(K, certified)
-        e3 = torch.cuda.Event(enable_timing=True)
-        e4 = torch.cuda.Event(enable_timing=True)
-        V.zero_()
-        e3.record(stream)
-        s3 = mb.vi_solve(h32, V, best_b, seed, ws, tol_dv=-1.0, eps=args.eps, V_ref=Vref32,
-                         max_sweeps=20000)
-        e4.record(stream)
-        e4.synchronize()
-        t_f32 = e3.elapsed_time(e4)
+        for stored, K, certified in (("vi", 0, True), ("vi", K_mpi, True), ("mpi", K_mpi, True),
+                                     ("vi", 0, False), ("mpi", K_mpi, False)):
+            lp_run(stored, K, certified)  # warm-up
+            runs["%s_k%d_%s" % (stored, K, "certified" if certified else "measured")] = \
+                lp_run(stored, K, certified)
+        f32 = {}
+        for solver in ("vi", "mpi"):
+            for _ in range(2):  # warm-up, then timed
+                e3 = torch.cuda.Event(enable_timing=True)
+                e4 = torch.cuda.Event(enable_timing=True)
+                V.zero_()
+                pol.zero_()
+                e3.record(stream)
+                if solver == "vi":
+                    s3 = mb.vi_solve(h32, V, best_b, seed, ws, tol_dv=-1.0, eps=args.eps,
+                                     V_ref=Vref32, max_sweeps=20000)
+                else:
+                    s3 = mb.mpi_solve(h32, V, pol, K_mpi, best_b, seed, ws, policy_is_init=False,
+                                      tol_dv=-1.0, eps=args.eps, V_ref=Vref32, max_outer=4000)
+                e4.record(stream)
+                e4.synchronize()
+            f32[solver] = {"sweeps": s3["sweeps"], "improvements": s3["outer_iters"],
+                           "ms": e3.elapsed_time(e4),
+                           "rule": "first sweep with max|V - J*(FP32)| <= eps"}
+            log("FP32 alone (%s): %d sweeps %.1f ms" % (solver, s3["sweeps"], f32[solver]["ms"]))
+        best_lp = min(runs, key=lambda k: runs[k]["total_ms"] if k.endswith("measured") else 1e30)
+        best_cert = min(runs, key=lambda k: runs[k]["total_ms"] if k.endswith("certified")
+                        else 1e30)
+        best_f32 = min(f32, key=lambda k: f32[k]["ms"])
         precision = {
             "storage": args.precision,
             "err_stored_vs_f32_solution": lp_err,
-            "stored_solve_tol_dv": tol_stored,
+            "stored_solve_stop": "certified max|V - J*(stored)| <= err_stored_vs_f32_solution",
             "stored_then_fp64_correction": runs,
-            "f32_alone": {"sweeps": s3["sweeps"], "ms": t_f32,
-                          "rule": "first sweep with max|V - J*(FP32)| <= eps"},
+            "f32_alone": f32,
+            "equal_accuracy": {"eps": args.eps, "best_stored_then_correction": best_lp,
+                               "ms": runs[best_lp]["total_ms"], "best_f32_alone": best_f32,
+                               "f32_ms": f32[best_f32]["ms"],
+                               "speedup": f32[best_f32]["ms"] / runs[best_lp]["total_ms"]},
+            "best_certified": {"run": best_cert, "ms": runs[best_cert]["total_ms"],
+                               "bound": runs[best_cert]["fp64_correction"]["certified_bound"]},
         }
-        log("FP32 alone: %d sweeps %.1f ms" % (s3["sweeps"], t_f32))
 
     line = {
         "metric": METRIC,

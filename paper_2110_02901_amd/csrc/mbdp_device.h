@@ -230,8 +230,17 @@ __device__ __forceinline__ bool grid_sync(GridBarrier& g) {
   if (blockIdx.x == 0) {
     for (unsigned i = threadIdx.x; i < g.nblocks && ok; i += blockDim.x)
       ok = wait_at_least(&slots[i], g.gen, g);
+    // Workgroup 0 relays the arrivals: an acquire after observing them and a
+    // release before publishing make every arrival happen before the release
+    // word's store, so each workgroup's acquire below synchronises with all
+    // arrivals through workgroup 0 (release -> acquire at agent scope, then
+    // the workgroup barrier, then release -> acquire again).
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __syncthreads();
-    if (threadIdx.x == 0) atomic_store_agent(&g.ctl->bar_release, g.gen);
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      atomic_store_agent(&g.ctl->bar_release, g.gen);
+    }
   }
   if (threadIdx.x == 0) {
     if (ok) ok = wait_at_least(&g.ctl->bar_release, g.gen, g);
