@@ -475,7 +475,9 @@ def run_batch(args, dev):
         "config": {"workload": "batch-512", "count": count, "n": "U[256, 4096]", "m": m,
                    "alpha": 1.0, "gamma": "U[0.9, 0.99]",
                    "b": "ceil(n / 8)" if tuned_b is None else "ceil(n / d), d tuned: %s" % tuned_b,
-                   "storage": "bf16", "tol_dv": tol, "launch": "hipGraph replay"},
+                   "storage": "bf16", "tol_dv": tol, "launch": "hipGraph replay",
+                   "accumulate": "f64 (rows decoded exactly, FP64 FMA; a departure from the "
+                                 "workload's FP32 accumulation)"},
         "hbm_gbps": gbps,
         "sweeps": {"min": min(sweeps), "max": max(sweeps), "mean": float(np.mean(sweeps))},
         "schedule": {"span_ms": span / 1e3, "cu_busy": busy / (cus * span),
