@@ -276,6 +276,30 @@ mbdp_status mdp_multi_solve(mbdp_mdp_t h, int32_t r, const float* C, double* V, 
                             int64_t max_sweeps, void* workspace, size_t ws_bytes,
                             hipStream_t stream, mbdp_multi_stats* stats);
 
+/* Column-sorted blocks for b = n (an MI355X layout; the method is unchanged).
+ * With b = n the whole state set is one batch that reads only the values
+ * from before it (eq. (11) with an empty updated set: the Bellman operator T,
+ * eq. (7)), so a backup's products may be summed in any order.  For a
+ * constant-row-length FP32 MDP with n <= 2^20 states (and m <= 4096) the
+ * library can keep a second copy of the entries, grouped by blocks of
+ * 4096 / m states and sorted by column inside each block, packed into groups
+ * of 64 entries with distinct rows (padding entries have value 0): the V
+ * gathers of a wavefront then fall on a few cache lines instead of 64, and
+ * the products are summed in LDS without atomics.  Solves and sweeps with
+ * b = n (min and improvement passes) then run the "ell-colblock" kernel;
+ * policy sweeps and b < n keep the row-major kernels.  The sums are
+ * grouped differently from the row-major kernels (FP32 rounding differs;
+ * results are deterministic).
+ * mdp_column_blocks_prepare copies col / val to the host, builds the layout
+ * on host threads and returns in *bytes the device buffer it needs (about
+ * 8 bytes per entry); synchronises `stream`.  mdp_column_blocks_attach
+ * copies it into `buffer` (device, 256-byte aligned, at least *bytes,
+ * borrowed like the other arrays) and releases the host copy; synchronises
+ * `stream`.  MBDP_ERR_UNSUPPORTED for other MDPs. */
+mbdp_status mdp_column_blocks_prepare(mbdp_mdp_t h, hipStream_t stream, size_t* bytes);
+mbdp_status mdp_column_blocks_attach(mbdp_mdp_t h, void* buffer, size_t bytes,
+                                     hipStream_t stream);
+
 /* Replaces the handle's tuning knobs. */
 mbdp_status mdp_set_tuning(mbdp_mdp_t h, const mbdp_tuning* t);
 
@@ -288,7 +312,7 @@ size_t mdp_workspace_bytes(mbdp_mdp_t h, int64_t b);
  * "ell" (constant row length, V gathered from memory), "ell-band" (constant
  * row length with every column within a band around its state: each
  * workgroup owns a chunk of states and stages the band of V it reads in
- * LDS) or "csr".  The choice follows the handle's tuning.  *name points to
+ * LDS), "ell-colblock" (b = n with column blocks attached) or "csr".  The choice follows the handle's tuning.  *name points to
  * a static string.  No device work. */
 mbdp_status mdp_engine(mbdp_mdp_t h, int64_t b, const char** name);
 

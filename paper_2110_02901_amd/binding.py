@@ -40,6 +40,7 @@ EXPORTS = [
     "mdp_quantize_rows", "mdp_policy_transpose", "mdp_value_gradients", "mdp_destroy",
     "mdp_set_tuning", "mdp_batch_workspace_bytes", "mdp_batch_upload", "mdp_batch_launch",
     "mdp_batch_read_stats", "mdp_multi_workspace_bytes", "mdp_multi_solve",
+    "mdp_column_blocks_prepare", "mdp_column_blocks_attach",
     "mdp_workspace_bytes", "mdp_engine", "mdp_validate", "mbdp_permutation", "mb_sweep",
     "mbdp_sync_status", "vi_solve", "vi_solve_noalloc", "mpi_solve", "mdp_refine",
     "mbdp_last_error",
@@ -140,6 +141,8 @@ _SIGS = {
                                ctypes.c_size_t, _P, ctypes.POINTER(MultiStats)]),
     "mdp_value_gradients": (_I32, [_P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "mdp_set_tuning": (_I32, [_P, ctypes.POINTER(Tuning)]),
+    "mdp_column_blocks_prepare": (_I32, [_P, _P, ctypes.POINTER(ctypes.c_size_t)]),
+    "mdp_column_blocks_attach": (_I32, [_P, _P, ctypes.c_size_t, _P]),
     "mdp_workspace_bytes": (ctypes.c_size_t, [_P, _I64]),
     "mdp_engine": (_I32, [_P, _I64, ctypes.POINTER(ctypes.c_char_p)]),
     "mdp_validate": (_I32, [_P, _D, _P, ctypes.c_size_t, _P, ctypes.POINTER(Validation)]),
@@ -409,6 +412,19 @@ def mdp_batch_read_stats(ws, count, stream=None):
 
 def mdp_destroy(h):
     h.close()
+
+
+def mdp_column_blocks(h, stream=None):
+    """Builds and attaches the column-sorted blocks (b = n kernel) of an
+    ELL FP32 handle; returns the device buffer, which the handle keeps."""
+    import torch
+    nbytes = ctypes.c_size_t(0)
+    _check(lib().mdp_column_blocks_prepare(h.ptr, _stream(stream), ctypes.byref(nbytes)))
+    buf = torch.empty((nbytes.value + 255) // 256 * 256 // 4, dtype=torch.int32,
+                      device=torch.device("cuda", torch.cuda.current_device()))
+    _check(lib().mdp_column_blocks_attach(h.ptr, _ptr(buf), buf.numel() * 4, _stream(stream)))
+    h._keep = list(h._keep) + [buf]
+    return buf
 
 
 def mdp_set_tuning(h, blocks_per_cu=0, threads_per_block=0, recentre_every=0, recentre_force=0,

@@ -1114,6 +1114,113 @@ struct BandEngine : EllEngine<UNR, LPR, T> {
   }
 };
 
+// ------------------------------------------------------------ column-block engine
+//
+// For b = n (the whole state set is one batch, which reads only the values
+// before it: eq. (11) with M_n(i) empty, i.e. T of eq. (7)) the order in
+// which a batch's products are summed is free.  A constant-row-length MDP
+// may then carry a second copy of its entries in column-sorted blocks
+// (mdp_column_blocks_prepare / _attach): block B holds the entries of the
+// rows of states [B * bs, (B + 1) * bs) (bs * m <= 4096 rows), sorted by
+// column and packed into groups of 64 entries whose rows are distinct, each
+// entry a 32-bit key (column << 12 | row within the block) and an FP32 value
+// (padding entries have value 0).  A workgroup takes a block, its waves take
+// the groups in turn and gather V for a group's 64 columns -- sorted, so
+// they fall on a few cache lines instead of 64 -- then add value * V into
+// the wave's own copy of the block's row sums in LDS (the rows of a group
+// are distinct, so a wave's 64 lanes never collide, and no other wave
+// writes that copy: no atomics).  The copies are summed in a fixed order
+// per row, the cost added in FP64, the minimum taken and committed as by
+// the other engines.  Policy sweeps (one row per state) and b < n use the
+// row-major engine, whose re-centring pass is also used.
+constexpr int kColWaves = 8;     // wavefronts per workgroup, one LDS copy each
+
+struct ColShared {
+  float acc[kColWaves][kColRows];
+};
+
+__device__ __forceinline__ ColShared& col_shared() {
+  __shared__ ColShared sh;
+  return sh;
+}
+
+template <int UNR, int LPR>
+struct ColEngine : EllEngine<UNR, LPR, ValF32> {
+  static constexpr bool kBand = false;
+  using Base = EllEngine<UNR, LPR, ValF32>;
+  using Acc = typename Base::Acc;
+  static constexpr int U = 4;  // groups of 64 entries in flight per wavefront
+
+  template <bool CE, bool IDENT, class Acc>
+  __device__ __forceinline__ static void batch(const KParams& p, const int32_t* ord, int64_t bk,
+                                               const Ctx& c, int mode, Acc& L) {
+    if (mode == kModePolicy || bk != p.n || !p.cb_keys || (blockDim.x >> 6) > kColWaves) {
+      Base::template batch<CE, IDENT>(p, ord, bk, c, mode, L);
+      return;
+    }
+    float(&acc)[kColWaves][kColRows] = col_shared().acc;
+    const int m = p.m;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int W = (int)(blockDim.x >> 6);  // <= kColWaves (the launch uses 512 threads)
+    const int64_t bs = p.cb_states, n = p.n;
+    const int rows_blk = (int)bs * m;
+    const int64_t nblk = (n + bs - 1) / bs;
+    const float* __restrict__ rd = c.rd;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+      const int64_t s0 = blk * bs;
+      const int ns = (int)min(bs, n - s0);
+      for (int i = threadIdx.x; i < W * kColRows; i += blockDim.x)
+        (&acc[0][0])[i] = 0.f;
+      __syncthreads();
+      const int64_t g0 = p.cb_gptr[blk], g1 = p.cb_gptr[blk + 1];
+      float* a = acc[wv];
+      for (int64_t gg = g0 + wv; gg < g1; gg += (int64_t)W * U) {
+        uint32_t kk[U];
+        float vv[U], gv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t gr = gg + (int64_t)u * W;
+          const bool ok = gr < g1;
+          const size_t e = (size_t)(ok ? gr : g0) * kWave + lane;  // a valid group either way
+          kk[u] = __builtin_nontemporal_load(p.cb_keys + e);
+          vv[u] = ok ? __builtin_nontemporal_load(p.cb_vals + e) : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) gv[u] = rd[kk[u] >> 12];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t r = kk[u] & (kColRows - 1);
+          a[r] = fmaf(vv[u], gv[u], a[r]);
+        }
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+        const int32_t s = (int32_t)(s0 + i);
+        const float old = rd[s];
+        const double aux = commit_aux<CE, IDENT>(p, s);
+        double qb = INFINITY;
+        int ab = 0;
+        for (int act = 0; act < m; ++act) {
+          const int r = i * m + act;
+          float sum = 0.f;
+          for (int w = 0; w < W; ++w) sum += acc[w][r];
+          const double q = cost_of<CE>(p, (int64_t)s * m + act) + p.gamma * (double)sum;
+          if (q < qb) {  // ascending actions: strictly smaller keeps the lowest
+            qb = q;
+            ab = act;
+          }
+        }
+        if (mode >= kModeImprove)
+          commit_improve(p, s, qb, ab, old, mode == kModeImproveCount, aux, L);
+        else
+          commit_sweep(p, c, s, qb, ab, old, aux, L);
+      }
+      __syncthreads();  // the copies are cleared for the next block
+      (void)rows_blk;
+    }
+  }
+};
+
 // ------------------------------------------------------------ general CSR engine
 
 struct CsrEngine {

@@ -115,6 +115,11 @@ struct KParams {
   float* partial;          // dense split partial sums
   unsigned int* unit_count;// dense split arrival counters
   unsigned long long timeout_ticks;
+  // column-sorted blocks of a constant-row-length FP32 MDP (b = n), or null
+  const uint32_t* cb_keys;  // [groups * 64]: column << 12 | row within the block
+  const float* cb_vals;     // [groups * 64]
+  const int32_t* cb_gptr;   // [blocks + 1]: first group of each block
+  int64_t cb_states;        // states per block
 };
 
 // Workspace layout, shared by the size query and the launches.
@@ -157,7 +162,11 @@ struct LaunchShape {
 constexpr int kMaxBlocksPerCu = 16;
 
 // Kernel families a launch can run.
-enum Engine : int { kEngineDense = 0, kEngineEll = 1, kEngineBand = 2, kEngineCsr = 3 };
+enum Engine : int { kEngineDense = 0, kEngineEll = 1, kEngineBand = 2, kEngineCsr = 3,
+                     kEngineCol = 4 };
+constexpr int kColThreads = 512;  // threads of a column-block launch (8 wavefronts)
+constexpr int kColRows = 4096;    // rows per column block (the 12-bit row field of a key)
+constexpr int kColGroup = 64;     // entries per group (one per lane of a wavefront)
 
 // Fills p.splits from the grid actually used and launches the persistent
 // kernel cooperatively.  Returns 0 or -1 with a message in err.

@@ -369,6 +369,21 @@ static SolveFn pick_band(const KParams& p, int units_per_wave_hint) {
   }
 }
 
+// The column-block instantiation (b = n with an attached layout), or null.
+static SolveFn pick_col(const KParams& p, int units_per_wave_hint) {
+  int lpr = 1;
+  while (lpr * 4 < p.ell_k) lpr <<= 1;
+  const bool two = units_per_wave_hint >= 2;
+  switch (lpr) {
+    case 1: return two ? solve_fn<ColEngine<2, 1>>(p.task) : solve_fn<ColEngine<1, 1>>(p.task);
+    case 2: return two ? solve_fn<ColEngine<2, 2>>(p.task) : solve_fn<ColEngine<1, 2>>(p.task);
+    case 4: return two ? solve_fn<ColEngine<2, 4>>(p.task) : solve_fn<ColEngine<1, 4>>(p.task);
+    case 8: return two ? solve_fn<ColEngine<2, 8>>(p.task) : solve_fn<ColEngine<1, 8>>(p.task);
+    case 16: return two ? solve_fn<ColEngine<2, 16>>(p.task) : solve_fn<ColEngine<1, 16>>(p.task);
+    default: return nullptr;
+  }
+}
+
 // Whether the band-local engine's LDS holds a chunk, its window and the
 // batch offsets for a grid of `blocks` workgroups.
 static bool band_fits(const KParams& p, int blocks) {
@@ -394,8 +409,29 @@ static int grid_blocks(SolveFn f, const LaunchShape& shape, int* blocks, char* e
 }
 
 // The instantiation a launch runs and its grid.
-static int choose(const KParams& p, const LaunchShape& shape, SolveFn* fn, int* blocks,
+static int choose(const KParams& p, LaunchShape& shape, SolveFn* fn, int* blocks,
                   int* engine, char* err, size_t errlen) {
+  // a banded MDP keeps the band-local engine (its V window in LDS beats the
+  // column blocks); otherwise, at b = n with column blocks attached, those
+  bool band_ok = false;
+  if (p.storage == kEll && p.band >= 0 && !p.perm && p.vdtype == kF32) {
+    SolveFn fb = pick_band(p, 1);
+    int bb = 0;
+    if (fb && grid_blocks(fb, shape, &bb, err, errlen) == 0) band_ok = band_fits(p, bb);
+  }
+  if (!band_ok && p.storage == kEll && p.cb_keys && p.b == p.n && p.vdtype == kF32) {
+    LaunchShape cs = shape;
+    cs.threads = kColThreads;
+    const int64_t waves = (int64_t)cs.cus * cs.blocks_per_cu * (kColThreads / kWave);
+    const int64_t per_wave = waves > 0 ? p.b / waves : 1;
+    SolveFn fc = pick_col(p, (int)(per_wave > 4 ? 4 : per_wave));
+    if (fc) {
+      shape = cs;
+      *fn = fc;
+      *engine = kEngineCol;
+      return grid_blocks(fc, shape, blocks, err, errlen);
+    }
+  }
   const int waves_per_block = shape.threads / kWave;
   // ELL: states per wavefront iteration from the batch size and a full grid
   const int64_t waves_guess = (int64_t)shape.cus * shape.blocks_per_cu * waves_per_block;

@@ -16,6 +16,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "mbdp.h"
@@ -43,6 +44,16 @@ struct mbdp_mdp {
   int cus;
   unsigned long long wall_khz;
   mbdp_tuning tuning;
+  // column-sorted blocks (constant row length, FP32, b = n): the host layout
+  // of mdp_column_blocks_prepare until mdp_column_blocks_attach copies it
+  // into the caller's buffer
+  std::vector<uint32_t> cb_keys_h;
+  std::vector<float> cb_vals_h;
+  std::vector<int32_t> cb_gptr_h;
+  int64_t cb_states = 0;
+  const uint32_t* cb_keys = nullptr;
+  const float* cb_vals = nullptr;
+  const int32_t* cb_gptr = nullptr;
 };
 
 namespace {
@@ -150,6 +161,10 @@ KParams base_params(const mbdp_mdp* h, void* ws, float* V, int64_t b) {
   p.timeout_ticks = (unsigned long long)(kBarrierTimeoutSeconds * 1000.0 * (double)h->wall_khz);
   p.tol_dv = -1.0;
   p.splits = 1;
+  p.cb_keys = h->cb_keys;
+  p.cb_vals = h->cb_vals;
+  p.cb_gptr = h->cb_gptr;
+  p.cb_states = h->cb_states;
   return p;
 }
 
@@ -409,8 +424,161 @@ mbdp_status mdp_engine(mbdp_mdp_t h, int64_t b, const char** name) {
   int engine = 0;
   char err[256] = {0};
   if (query_engine(p, shape_of(h), &engine, err, sizeof err) != 0) return fail(MBDP_ERR_HIP, "%s", err);
-  static const char* const names[] = {"dense", "ell", "ell-band", "csr"};
+  static const char* const names[] = {"dense", "ell", "ell-band", "csr", "ell-colblock"};
   *name = names[engine];
+  return MBDP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int64_t kColMaxStates = (int64_t)1 << 20;  // 20-bit column field of a key
+
+struct ColLayoutSizes {
+  size_t gptr, keys, vals, total;
+};
+
+ColLayoutSizes col_sizes(const mbdp_mdp* h) {
+  ColLayoutSizes z{};
+  z.gptr = 0;
+  z.keys = align_up(h->cb_gptr_h.size() * sizeof(int32_t), 256);
+  z.vals = align_up(z.keys + h->cb_keys_h.size() * sizeof(uint32_t), 256);
+  z.total = align_up(z.vals + h->cb_vals_h.size() * sizeof(float), 256);
+  return z;
+}
+
+// Entries of block b (states [b bs, (b + 1) bs)) sorted by column, then
+// packed greedily into groups of 64 with distinct rows (an entry whose row
+// is already in the current group waits for the next one, ahead of the
+// rest); the last group is padded with zero values on unused rows.
+void build_col_block(const int32_t* col, const float* val, int64_t n, int32_t m, int32_t k,
+                     int64_t bs, int64_t b, std::vector<uint32_t>& keys, std::vector<float>& vals) {
+  const int64_t r0 = b * bs * m, r1 = std::min(n, (b + 1) * bs) * m;
+  std::vector<std::pair<uint32_t, float>> e;
+  e.reserve((size_t)(r1 - r0) * k);
+  for (int64_t r = r0; r < r1; ++r)
+    for (int32_t i = 0; i < k; ++i) {
+      const size_t x = (size_t)r * k + i;
+      e.push_back({((uint32_t)col[x] << 12) | (uint32_t)(r - r0), val[x]});
+    }
+  std::stable_sort(e.begin(), e.end(),
+                   [](const std::pair<uint32_t, float>& a, const std::pair<uint32_t, float>& c) {
+                     return a.first < c.first;
+                   });
+  std::vector<int> mark(kColRows, -1);
+  std::vector<std::pair<uint32_t, float>> pend, next;
+  size_t i = 0;
+  int group = 0;
+  while (i < e.size() || !pend.empty()) {
+    int cnt = 0;
+    uint32_t last = 0;
+    next.clear();
+    auto take = [&](const std::pair<uint32_t, float>& x) {
+      const uint32_t r = x.first & (kColRows - 1);
+      if (mark[r] == group) return false;
+      mark[r] = group;
+      keys.push_back(x.first);
+      vals.push_back(x.second);
+      last = x.first;
+      ++cnt;
+      return true;
+    };
+    for (size_t q = 0; q < pend.size(); ++q)
+      if (cnt == kColGroup || !take(pend[q])) next.push_back(pend[q]);
+    pend.swap(next);
+    while (i < e.size() && cnt < kColGroup)
+      if (!take(e[i++])) pend.push_back(e[i - 1]);
+    for (uint32_t r = 0; cnt < kColGroup; ++r)
+      if (mark[r] != group) {
+        mark[r] = group;
+        keys.push_back((last & ~(uint32_t)(kColRows - 1)) | r);
+        vals.push_back(0.f);
+        ++cnt;
+      }
+    ++group;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+mbdp_status mdp_column_blocks_prepare(mbdp_mdp_t h, hipStream_t stream, size_t* bytes) {
+  if (!h || !bytes) return fail(MBDP_ERR_INVALID_ARG, "handle or bytes is NULL");
+  *bytes = 0;
+  if (h->storage != kEll || h->vdtype != kF32)
+    return fail(MBDP_ERR_UNSUPPORTED, "column blocks need constant-row-length FP32 rows");
+  if (h->n > kColMaxStates)
+    return fail(MBDP_ERR_UNSUPPORTED, "column blocks need n <= 2^20 (n = %lld)", (long long)h->n);
+  if (h->m > kColRows) return fail(MBDP_ERR_UNSUPPORTED, "column blocks need m <= %d", kColRows);
+  const int64_t n = h->n, bs = kColRows / h->m, nblk = (n + bs - 1) / bs;
+  const size_t nnz = (size_t)h->nnz;
+  std::vector<int32_t> col(nnz);
+  std::vector<float> val(nnz);
+  MBDP_HIP(hipMemcpyAsync(col.data(), h->col, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  MBDP_HIP(hipMemcpyAsync(val.data(), h->val, nnz * sizeof(float), hipMemcpyDeviceToHost, stream));
+  MBDP_HIP(hipStreamSynchronize(stream));
+  // blocks are built on host threads, each over a contiguous range of
+  // blocks, then concatenated in block order (the result does not depend
+  // on the thread count)
+  unsigned nt = std::thread::hardware_concurrency();
+  nt = std::max(1u, std::min(nt, 32u));
+  std::vector<std::vector<uint32_t>> tk(nt);
+  std::vector<std::vector<float>> tv(nt);
+  std::vector<std::vector<int64_t>> tg(nt);  // groups per block
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t)
+    th.emplace_back([&, t] {
+      const int64_t b0 = nblk * t / nt, b1 = nblk * (t + 1) / nt;
+      for (int64_t b = b0; b < b1; ++b) {
+        const size_t before = tk[t].size();
+        build_col_block(col.data(), val.data(), n, h->m, h->ell_k, bs, b, tk[t], tv[t]);
+        tg[t].push_back((int64_t)((tk[t].size() - before) / kColGroup));
+      }
+    });
+  for (auto& x : th) x.join();
+  h->cb_keys_h.clear();
+  h->cb_vals_h.clear();
+  h->cb_gptr_h.assign(1, 0);
+  int64_t groups = 0;
+  for (unsigned t = 0; t < nt; ++t) {
+    h->cb_keys_h.insert(h->cb_keys_h.end(), tk[t].begin(), tk[t].end());
+    h->cb_vals_h.insert(h->cb_vals_h.end(), tv[t].begin(), tv[t].end());
+    for (int64_t g : tg[t]) {
+      groups += g;
+      if (groups > INT32_MAX) return fail(MBDP_ERR_UNSUPPORTED, "too many column-block groups");
+      h->cb_gptr_h.push_back((int32_t)groups);
+    }
+  }
+  h->cb_states = bs;
+  *bytes = col_sizes(h).total;
+  return MBDP_OK;
+}
+
+mbdp_status mdp_column_blocks_attach(mbdp_mdp_t h, void* buffer, size_t bytes,
+                                     hipStream_t stream) {
+  if (!h || !buffer) return fail(MBDP_ERR_INVALID_ARG, "handle or buffer is NULL");
+  if (h->cb_gptr_h.empty())
+    return fail(MBDP_ERR_INVALID_ARG, "no column blocks prepared (mdp_column_blocks_prepare)");
+  if (((uintptr_t)buffer) % 256) return fail(MBDP_ERR_INVALID_ARG, "buffer is not 256-byte aligned");
+  const ColLayoutSizes z = col_sizes(h);
+  if (bytes < z.total)
+    return fail(MBDP_ERR_INVALID_ARG, "buffer has %zu bytes, need %zu", bytes, z.total);
+  char* base = static_cast<char*>(buffer);
+  MBDP_HIP(hipMemcpyAsync(base + z.gptr, h->cb_gptr_h.data(),
+                          h->cb_gptr_h.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  MBDP_HIP(hipMemcpyAsync(base + z.keys, h->cb_keys_h.data(),
+                          h->cb_keys_h.size() * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
+  MBDP_HIP(hipMemcpyAsync(base + z.vals, h->cb_vals_h.data(),
+                          h->cb_vals_h.size() * sizeof(float), hipMemcpyHostToDevice, stream));
+  MBDP_HIP(hipStreamSynchronize(stream));
+  h->cb_gptr = reinterpret_cast<const int32_t*>(base + z.gptr);
+  h->cb_keys = reinterpret_cast<const uint32_t*>(base + z.keys);
+  h->cb_vals = reinterpret_cast<const float*>(base + z.vals);
+  std::vector<uint32_t>().swap(h->cb_keys_h);
+  std::vector<float>().swap(h->cb_vals_h);
+  std::vector<int32_t>().swap(h->cb_gptr_h);
   return MBDP_OK;
 }
 

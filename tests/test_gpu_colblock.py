@@ -1,0 +1,171 @@
+"""GPU parity of the column-block kernel (b = n on constant-row-length FP32
+MDPs with the column-sorted layout attached) against the oracle.
+
+With b = n every state reads the values from before the sweep (eq. (11),
+the Bellman operator T of eq. (7)), so the kernel may sum a backup's
+products in any grouping; it is checked like the row-major kernels: one
+sweep from a seeded V against the oracle's (max abs error <= 1e-5 max abs
+V, argmin exact where the Q-gap exceeds the tolerance), improvement passes
+through MPI, VI and MPI to J* (policy iteration) within eps, ragged shapes
+(several m, a short last block), the full 1M-state uniform workload, and
+the argument checks.  b < n keeps the row-major kernels."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2110_02901_amd import binding as mb
+from paper_2110_02901_amd import inputs
+
+from gpu_util import csr_case, dev, run_sweep, up
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print("[colblock] " + msg, flush=True)
+
+
+def out_tol(eps, Vstar):
+    return eps + 0.5 * float(np.spacing(np.float32(np.max(np.abs(Vstar)))))
+
+
+@pytest.mark.parametrize("n,m,k,band", [(3000, 8, 32, None), (3000, 8, 32, 64), (2500, 5, 12, None),
+                                        (1000, 16, 8, None), (777, 1, 4, None), (4100, 3, 64, None)])
+def test_sweeps_match_oracle(n, m, k, band):
+    rp, col, val, c = inputs.csr_mdp(n, m, k, 1.0, 31, band=band)
+    h, mdp = csr_case(rp, col, val, c, 0.99)
+    mb.mdp_column_blocks(h)
+    # the band-local engine is preferred wherever its window fits (the band
+    # here, or all of V for these small n); switched off, the column blocks run
+    assert mb.mdp_engine(h, n) in ("ell-band", "ell-colblock")
+    mb.mdp_set_tuning(h, band_window=-1)
+    assert mb.mdp_engine(h, n) == "ell-colblock"
+    assert mb.mdp_engine(h, n - 1) in ("ell", "ell-band")
+    V0 = inputs.values(n, 32, 10.0, 20.0)
+    for t in range(3):
+        run_sweep(h, mdp, V0, n, 104, t)
+    # a policy sweep at b = n runs the row-major kernel on the same handle
+    run_sweep(h, mdp, V0, n, 104, 5, policy=inputs.policy(n, m, 33))
+
+
+@pytest.fixture(scope="module")
+def uni3000():
+    rp, col, val, c = inputs.csr_mdp(3000, 8, 32, 1.0, 34, band=None)
+    h, mdp = csr_case(rp, col, val, c, 0.995)
+    mb.mdp_column_blocks(h)
+    mb.mdp_set_tuning(h, band_window=-1)
+    assert mb.mdp_engine(h, 3000) == "ell-colblock"
+    Vstar, _, _ = oracle.policy_iteration(mdp)
+    return h, mdp, Vstar
+
+
+def test_vi_reaches_eps(uni3000):
+    h, mdp, Vstar = uni3000
+    ws = mb.workspace(h, 3000)
+    V = torch.zeros(3000, dtype=torch.float32, device=dev())
+    V64 = torch.zeros(3000, dtype=torch.float64, device=dev())
+    pol = torch.zeros(3000, dtype=torch.int32, device=dev())
+    st = mb.vi_solve(h, V, 3000, 105, ws, tol_dv=-1.0, eps=1e-6, V_ref=up(Vstar),
+                     max_sweeps=20000, V64_out=V64, policy_out=pol)
+    _, _, ost = oracle.value_iteration(mdp, 3000, 105, tol_dv=-1, V_ref=Vstar, eps=1e-6)
+    say("VI b=n: %s; oracle %d sweeps" % (st, ost.sweeps))
+    assert st["converged"]
+    assert np.max(np.abs(V64.cpu().numpy() - Vstar)) <= 1e-6
+    assert np.max(np.abs(V.cpu().numpy() - Vstar)) <= out_tol(1e-6, Vstar)
+    assert abs(st["sweeps"] - ost.sweeps) <= 2
+    Q = oracle.q_values(mdp, np.arange(3000), Vstar)
+    chosen = Q[np.arange(3000), pol.cpu().numpy()]
+    assert np.all(chosen <= Q.min(axis=1) + 1e-5)
+
+
+def test_mpi_reaches_eps_and_stops_on_its_rule(uni3000):
+    h, mdp, Vstar = uni3000
+    ws = mb.workspace(h, 3000)
+    V = torch.zeros(3000, dtype=torch.float32, device=dev())
+    V64 = torch.zeros(3000, dtype=torch.float64, device=dev())
+    pol = torch.zeros(3000, dtype=torch.int32, device=dev())
+    st = mb.mpi_solve(h, V, pol, 5, 3000, 106, ws, policy_is_init=False, tol_dv=1e-10,
+                      max_outer=20000, V64_out=V64)
+    say("MPI b=n: %s" % st)
+    assert st["converged"] and st["policy_changes_last"] == 0
+    assert np.max(np.abs(V64.cpu().numpy() - Vstar)) <= 1e-10 / (1 - 0.995) + 1e-9
+
+
+def test_same_iterates_as_the_row_major_kernel():
+    """Two handles on the same arrays, one with column blocks: 50 sweeps of
+    VI at b = n agree within FP32 rounding of the sums."""
+    rp, col, val, c = inputs.csr_mdp(5000, 8, 32, 1.0, 35, band=None)
+    arrays = [up(a) for a in (rp, col, val, c)]
+    h1 = mb.mdp_create_csr(*arrays, 0.99)
+    h2 = mb.mdp_create_csr(*arrays, 0.99)
+    mb.mdp_column_blocks(h2)
+    for h in (h1, h2):
+        mb.mdp_set_tuning(h, band_window=-1)
+    assert mb.mdp_engine(h1, 5000) == "ell" and mb.mdp_engine(h2, 5000) == "ell-colblock"
+    out = []
+    for h in (h1, h2):
+        V = torch.zeros(5000, dtype=torch.float32, device=dev())
+        V64 = torch.zeros(5000, dtype=torch.float64, device=dev())
+        mb.vi_solve(h, V, 5000, 107, mb.workspace(h, 5000), tol_dv=-1.0, max_sweeps=50,
+                    V64_out=V64)
+        out.append(V64.cpu().numpy())
+    diff = float(np.max(np.abs(out[0] - out[1])))
+    say("row-major vs column blocks after 50 sweeps: %.3g" % diff)
+    assert diff <= 1e-5 * float(np.max(np.abs(out[0])))
+
+
+def test_rejections():
+    P, c = inputs.dense_mdp(64, 4, 1.0, 1, dtype=np.float32)
+    hd = mb.mdp_create_dense(up(P), up(c), 0.9)
+    with pytest.raises(mb.MbdpError) as e:
+        mb.mdp_column_blocks(hd)
+    assert e.value.status == mb.MBDP_ERR_UNSUPPORTED
+    rp, col, val, c = inputs.csr_mdp(500, 4, 8, 1.0, 36)
+    q, s = mb.mdp_quantize_rows(up(val.reshape(2000, 8)), "bf16")
+    hq = mb.mdp_create_csr_q(up(rp), up(col), q.reshape(-1), "bf16", s, up(c), 0.9)
+    with pytest.raises(mb.MbdpError) as e:
+        mb.mdp_column_blocks(hq)
+    assert e.value.status == mb.MBDP_ERR_UNSUPPORTED
+    h = mb.mdp_create_csr(up(rp), up(col), up(val), up(c), 0.9)
+    buf = torch.empty(1024, dtype=torch.int32, device=dev())
+    assert mb.lib().mdp_column_blocks_attach(h.ptr, mb._ptr(buf), 4096, mb._stream(None)) == \
+        mb.MBDP_ERR_INVALID_ARG  # nothing prepared
+    import ctypes
+    nbytes = ctypes.c_size_t(0)
+    assert mb.lib().mdp_column_blocks_prepare(h.ptr, mb._stream(None), ctypes.byref(nbytes)) == 0
+    assert nbytes.value >= 500 * 4 * 8 * 8
+    assert mb.lib().mdp_column_blocks_attach(h.ptr, mb._ptr(buf), 4096, mb._stream(None)) == \
+        mb.MBDP_ERR_INVALID_ARG  # too small
+    assert mb.mdp_engine(h, 500) in ("ell", "ell-band")   # nothing attached yet
+
+
+def test_full_size_uniform():
+    """csr-1M-uniform with column blocks: one sweep at b = n against a full
+    oracle sweep, then VI at b = n to max abs dV <= 1e-11, certified by the
+    oracle's Bellman residual of the result (Sec. III-B)."""
+    wl = inputs.WORKLOADS["csr-1M-uniform"]
+    n = wl["n"]
+    t0 = time.time()
+    rp, col, val, c = inputs.csr_mdp(n, wl["m"], wl["k"], wl["alpha"], wl["data_seed"],
+                                     band=wl["band"])
+    h, mdp = csr_case(rp, col, val, c, wl["gamma"])
+    mb.mdp_column_blocks(h)
+    say("generated, uploaded and blocked in %.1f s" % (time.time() - t0))
+    assert mb.mdp_engine(h, n) == "ell-colblock"
+    V0 = inputs.values(n, 21, 21.0, 23.0)
+    run_sweep(h, mdp, V0, n, wl["perm_seed"], 0, check_arg=False)
+    ws = mb.workspace(h, n)
+    V = torch.zeros(n, dtype=torch.float32, device=dev())
+    V64 = torch.zeros(n, dtype=torch.float64, device=dev())
+    t0 = time.time()
+    st = mb.vi_solve(h, V, n, wl["perm_seed"], ws, tol_dv=1e-11, max_sweeps=30000, V64_out=V64)
+    say("VI b=n to max|dV| <= 1e-11: %s in %.1f s" % (st, time.time() - t0))
+    assert st["converged"]
+    Vg = V64.cpu().numpy()
+    TV, _ = oracle.greedy(mdp, Vg)
+    bound = float(np.max(np.abs(TV - Vg))) / (1 - wl["gamma"])
+    say("certified max|V - J*| <= %.3g" % bound)
+    assert bound <= 1e-6
