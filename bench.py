@@ -27,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+# batch size of each workload's counter runs: the one its bench line selects
+PROFILE_B = {"dense-8192x16": 1024, "csr-1M-banded": 1_000_000, "csr-1M-uniform": 1_000_000}
 METRIC = "state-action backups/s + HBM GB/s; time-to-ε=1e-6 vs batch size b"
 
 
@@ -497,9 +499,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    workloads = ["dense-8192x16", "csr-1M-banded", "csr-1M-uniform", "batch-512",
+                 "multi-8192x16"]
     ap.add_argument("--workload", default="dense-8192x16",
-                    choices=["dense-8192x16", "csr-1M-banded", "csr-1M-uniform", "batch-512",
-                             "multi-8192x16"])
+                    help="one of %s (with --profile-sweeps, a comma-separated list of the "
+                         "first three)" % ", ".join(workloads))
     ap.add_argument("--multi-r", type=int, default=32, choices=[16, 32, 48, 64],
                     help="multi-8192x16: number of cost vectors")
     ap.add_argument("--no-tune", action="store_true",
@@ -522,6 +526,10 @@ def main():
                     help="only run two vi_solve launches of exactly S and 3 S sweeps at the "
                          "first batch size (per-sweep counters: the difference of the two)")
     args = ap.parse_args()
+    names = args.workload.split(",")
+    if any(w not in workloads for w in names) or (len(names) > 1 and (
+            not args.profile_sweeps or any(w in ("batch-512", "multi-8192x16") for w in names))):
+        ap.error("--workload: %s" % args.workload)
     if args.gpus != 1:
         print("bench.py measures one GPU only: the mini-batch sweep is built and timed on a "
               "single MI355X (sharding over several GPUs is described, not implemented); "
@@ -544,8 +552,15 @@ def main():
         for _ in range(3):
             y.copy_(x)
         torch.cuda.synchronize()
+        # a second kernel of known bytes: a sum that reads the 1 GiB once
+        tot = 0.0
+        for _ in range(3):
+            tot += float(x.sum())
+        torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": x.numel() * 4,
-                          "copy_probe_bytes_written": y.numel() * 4, "launches": 3}))
+                          "copy_probe_bytes_written": y.numel() * 4, "launches": 3,
+                          "sum_probe_bytes_read": x.numel() * 4, "sum_launches": 3,
+                          "sum": tot}))
         return
     wl_name = args.workload
     if wl_name == "batch-512":
@@ -554,6 +569,21 @@ def main():
     if wl_name == "multi-8192x16":
         run_multi(args, dev)
         return
+    if args.profile_sweeps and "," in wl_name:
+        # counter runs of several workloads in one process (one rocprofv3 run)
+        for name in wl_name.split(","):
+            run_single(args, dev, name)
+        return
+    run_single(args, dev, wl_name)
+
+
+def run_single(args, dev, wl_name):
+    """One dense or sparse workload: the time-to-eps table, the timed steps
+    and the JSON line (or, with --profile-sweeps, the counter launches)."""
+    import torch
+    from paper_2110_02901_amd import binding as mb
+    from paper_2110_02901_amd import inputs
+
     wl = inputs.WORKLOADS[wl_name]
     n, m, gamma = wl["n"], wl["m"], wl["gamma"]
     seed = wl["perm_seed"]
@@ -605,11 +635,15 @@ def main():
     ws = mb.workspace(h, n)
 
     if args.profile_sweeps:
-        b = batch_sizes[0]
+        # the batch size each workload's bench line selects, unless given
+        b = batch_sizes[0] if args.batch_sizes else PROFILE_B.get(wl_name, batch_sizes[0])
         out = {"b": b, "engine": mb.mdp_engine(h, b), "launches": [],
                "algorithmic_bytes_per_sweep": n * m * bytes_per_backup,
                "sources_hash": sources_hash("solve")}
-        for sweeps in (args.profile_sweeps, 3 * args.profile_sweeps):
+        # a warm-up launch of S sweeps, then the S and 3S launches whose
+        # counter difference is the per-sweep traffic (same cache state before
+        # each); each launch is one solve_kernel dispatch after one zero_kernel
+        for sweeps in (args.profile_sweeps, args.profile_sweeps, 3 * args.profile_sweeps):
             V = torch.zeros(n, dtype=torch.float32, device=dev)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -619,7 +653,8 @@ def main():
             e1.synchronize()
             out["launches"].append({"sweeps": st["sweeps"], "recentrings": st["recentrings"],
                                     "ms": e0.elapsed_time(e1)})
-        print(json.dumps(out))
+        out["workload"] = wl_name
+        print(json.dumps(out), flush=True)
         return
 
     # Reference V* for the time-to-eps rule (not timed): MPI at b = n until

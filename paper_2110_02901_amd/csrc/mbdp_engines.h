@@ -1136,7 +1136,7 @@ struct BandEngine : EllEngine<UNR, LPR, T> {
 constexpr int kColWaves = 8;     // wavefronts per workgroup, one LDS copy each
 
 struct ColShared {
-  float acc[kColWaves][kColRows];
+  float acc[kColWaves][kColRows] __attribute__((aligned(16)));
 };
 
 __device__ __forceinline__ ColShared& col_shared() {
@@ -1149,7 +1149,7 @@ struct ColEngine : EllEngine<UNR, LPR, ValF32> {
   static constexpr bool kBand = false;
   using Base = EllEngine<UNR, LPR, ValF32>;
   using Acc = typename Base::Acc;
-  static constexpr int U = 4;  // groups of 64 entries in flight per wavefront
+  static constexpr int U = 8;  // groups of 64 entries in flight per wavefront
 
   template <bool CE, bool IDENT, class Acc>
   __device__ __forceinline__ static void batch(const KParams& p, const int32_t* ord, int64_t bk,
@@ -1169,8 +1169,8 @@ struct ColEngine : EllEngine<UNR, LPR, ValF32> {
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
       const int64_t s0 = blk * bs;
       const int ns = (int)min(bs, n - s0);
-      for (int i = threadIdx.x; i < W * kColRows; i += blockDim.x)
-        (&acc[0][0])[i] = 0.f;
+      for (int i = threadIdx.x; i < W * kColRows / 4; i += blockDim.x)
+        reinterpret_cast<f4*>(&acc[0][0])[i] = f4{0.f, 0.f, 0.f, 0.f};
       __syncthreads();
       const int64_t g0 = p.cb_gptr[blk], g1 = p.cb_gptr[blk + 1];
       float* a = acc[wv];
@@ -1538,10 +1538,23 @@ struct Driver {
   }
 };
 
-// One 1024-thread workgroup per CU is 4 waves per SIMD: let the compiler use
-// the 128 VGPRs that allows rather than serialise loads for occupancy.
+// Threads per workgroup and waves per SIMD of an engine's launch: one
+// 1024-thread workgroup per CU is 4 waves per SIMD, so the compiler may use
+// the 128 VGPRs that allows rather than serialise loads for occupancy; the
+// column-block engine runs 512-thread workgroups (its LDS holds one per CU),
+// 2 waves per SIMD and up to 256 VGPRs.
+template <class Eng>
+struct LaunchOf {
+  static constexpr int kThreads = 1024, kWavesPerEU = 4;
+};
+template <int UNR, int LPR>
+struct LaunchOf<ColEngine<UNR, LPR>> {
+  static constexpr int kThreads = kColThreads, kWavesPerEU = 2;
+};
+
 template <class Eng, int TASK>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ void __launch_bounds__(LaunchOf<Eng>::kThreads)
+    __attribute__((amdgpu_waves_per_eu(LaunchOf<Eng>::kWavesPerEU, LaunchOf<Eng>::kWavesPerEU)))
 solve_kernel(KParams p) {
   Driver<typename Eng::Acc> d(p);
   const int64_t n = p.n;
