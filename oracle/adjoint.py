@@ -21,16 +21,21 @@ import numpy as np
 from .bellman import CsrMDP, DenseMDP, _policy_matrix
 
 
-def adjoint(mdp, mu, w, iterative_tol=None):
+def adjoint(mdp, mu, w, iterative_tol=None, dense=False):
     """lambda solving (I - gamma P_mu)^T lambda = w (FP64): LAPACK for dense
-    storage, sparse LU for CSR, or -- when ``iterative_tol`` is given --
-    BiCGSTAB to that relative residual (for large random sparse matrices,
-    whose LU fills in)."""
+    storage (and for CSR storage with ``dense``: the matrix is formed densely
+    and solved by LU), sparse LU for CSR, or -- when ``iterative_tol`` is
+    given -- BiCGSTAB to that relative residual (for large random sparse
+    matrices, whose LU fills in)."""
     n = mdp.n
     Pm = _policy_matrix(mdp, mu)
     w = np.asarray(w, dtype=np.float64)
     if isinstance(mdp, DenseMDP):
         return np.linalg.solve((np.eye(n) - mdp.gamma * Pm).T, w)
+    if dense:
+        A = -mdp.gamma * Pm.T.toarray()
+        A[np.arange(n), np.arange(n)] += 1.0
+        return np.linalg.solve(A, w)
     import scipy.sparse as sp
     import scipy.sparse.linalg as spla
     A = (sp.identity(n, format="csr") - mdp.gamma * Pm).T.tocsr()
@@ -42,14 +47,14 @@ def adjoint(mdp, mu, w, iterative_tol=None):
     return x
 
 
-def value_gradients(mdp, mu, V, w, iterative_tol=None):
+def value_gradients(mdp, mu, V, w, iterative_tol=None, dense=False):
     """(lambda, dL/dc [n, m], dL/dP) for L = w^T V at the policy mu with
     V = J_mu.  dL/dP has P's shape for dense storage and one entry per stored
     value for CSR storage."""
     n, m = mdp.n, mdp.m
     mu = np.asarray(mu, dtype=np.int64)
     V = np.asarray(V, dtype=np.float64)
-    lam = adjoint(mdp, mu, w, iterative_tol)
+    lam = adjoint(mdp, mu, w, iterative_tol, dense)
     gc = np.zeros((n, m))
     gc[np.arange(n), mu] = lam
     if isinstance(mdp, DenseMDP):

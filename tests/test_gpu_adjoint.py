@@ -184,6 +184,15 @@ def test_adjoint_at_the_differentiation_workload():
         % (err_c, err_v, scale))
     assert err_c <= 1e-5 * scale
     assert err_v <= 1e-5 * scale * float(np.max(np.abs(Vs)))
+    # and against the dense FP64 linear solve of the adjoint equation (LU of the
+    # 16384 x 16384 matrix (I - gamma P_mu)^T)
+    t0 = time.time()
+    lam_d, gc_d, gv_d = adj.value_gradients(mdp, mus, Vs, w, dense=True)
+    say("dense FP64 LU adjoint in %.1f s: max |lambda_dense - lambda_iterative| = %.3g"
+        % (time.time() - t0, float(np.max(np.abs(lam_d - lam)))))
+    assert np.max(np.abs(lam_d - lam)) <= 1e-10 * scale
+    assert np.max(np.abs(gc - gc_d)) <= 1e-5 * scale
+    assert np.max(np.abs(gv - gv_d)) <= 1e-5 * scale * float(np.max(np.abs(Vs)))
     h = 1e-4
     c64, v64 = c.astype(np.float64), val.astype(np.float64)
     for s in _clear_states(mdp, 2, 29, iterative_tol=1e-14):

@@ -113,3 +113,20 @@ def test_iterative_adjoint_matches_sparse_lu():
     direct = adj.adjoint(mdp, mu, w)
     iterative = adj.adjoint(mdp, mu, w, iterative_tol=1e-13)
     assert np.max(np.abs(direct - iterative)) <= 1e-10 * np.max(np.abs(direct))
+
+
+def test_dense_lu_adjoint_of_csr_storage():
+    """The dense FP64 LU solve of a CSR MDP's adjoint equation against sparse
+    LU and against the dense MDP's LAPACK solve (the same matrix), and
+    against a planted transpose mistake (the non-transposed system)."""
+    mdp = _csr(300, 4, 12, 19, 0.97)
+    mu = np.random.Generator(np.random.Philox(8)).integers(0, 4, 300)
+    w = _w(300, 9)
+    lu = adj.adjoint(mdp, mu, w)
+    dn = adj.adjoint(mdp, mu, w, dense=True)
+    assert np.max(np.abs(dn - lu)) <= 1e-11 * np.max(np.abs(lu))
+    Pm = oracle.bellman._policy_matrix(mdp, mu).toarray()
+    wrong = np.linalg.solve(np.eye(300) - 0.97 * Pm, w)
+    assert np.max(np.abs(wrong - dn)) > 1e-3 * np.max(np.abs(dn))
+    # the defining equation, written out
+    assert np.max(np.abs(dn - 0.97 * Pm.T @ dn - w)) <= 1e-11 * np.max(np.abs(dn))
