@@ -302,6 +302,7 @@ struct MultiArgs {
   int32_t splits;
   int32_t* policy;       // [n][r] or null
   double* dvs;           // [n] max |dV| over the vectors per position of the sweep
+  int32_t* order;        // [n] sigma_t of the sweep being run, written at its start
   MultiControl* ctl;
 };
 
@@ -309,7 +310,7 @@ struct MultiArgs {
 inline int64_t multi_rows_per_wave(int32_t r) { return r; }
 
 struct MultiLayout {
-  size_t ctl, R, W, Ws, PR, part, dvs, total;
+  size_t ctl, R, W, Ws, PR, part, dvs, order, total;
   int64_t kchunk;
   int32_t splits;
 };
@@ -332,6 +333,7 @@ inline MultiLayout multi_layout(int64_t n, int32_t m, int32_t r, int64_t b) {
   l.PR = off;   off = align_up(off + (size_t)n * m * r * sizeof(double), 256);
   l.part = off; off = align_up(off + (size_t)l.splits * b * m * r * sizeof(float), 256);
   l.dvs = off;  off = align_up(off + (size_t)n * sizeof(double), 256);
+  l.order = off; off = align_up(off + (size_t)n * sizeof(int32_t), 256);
   l.total = off;
   return l;
 }
@@ -339,6 +341,7 @@ inline MultiLayout multi_layout(int64_t n, int32_t m, int32_t r, int64_t b) {
 int launch_multi_gemm(const MultiArgs& a, uint64_t t, int64_t k, int full, void* stream);
 int launch_multi_commit(const MultiArgs& a, uint64_t t, int64_t k, int mode, void* stream);
 int launch_multi_end(const MultiArgs& a, void* stream);
+int launch_multi_order(const MultiArgs& a, uint64_t t, void* stream);
 int launch_multi_anchor(const MultiArgs& a, double* V, int mode, void* stream);
 int launch_multi_pr(const MultiArgs& a, void* stream);
 

@@ -16,7 +16,8 @@
 // fraction of the current change per sweep by folding W into R (the same
 // idea as the single-vector anchor).
 //
-// One batch is two launches: `multi_gemm_kernel` writes the partial products
+// A sweep starts with `multi_order_kernel`, which writes sigma_t into a table
+// of the workspace.  One batch is two launches: `multi_gemm_kernel` writes the partial products
 // of a K-range of P per (row, vector) (split over K so that a batch of a few
 // thousand rows still fills the device), `multi_commit_kernel` adds the
 // partials in FP64 with the cost, the anchor share and the row scale, takes
@@ -53,13 +54,24 @@ __device__ __forceinline__ bool multi_done(const MultiControl* ctl) {
 }
 
 // Row `row` of a launch over positions kb, kb + 1, ... : its state and
-// action.  Positions are those of sweep order sigma_t, or (full) the states
-// themselves, for the greedy policy.
+// action.  Positions are those of sweep order sigma_t (the table the sweep's
+// order kernel wrote), or (full) the states themselves, for the greedy policy.
 __device__ __forceinline__ void multi_row_state(int64_t row, int32_t m, int full, int64_t kb,
-                                                const OrderKey& key, int64_t& s, int32_t& a) {
+                                                const int32_t* order, int64_t& s, int32_t& a) {
   const int64_t p = row / m;
   a = (int32_t)(row - p * m);
-  s = full ? kb + p : (int64_t)sweep_order_at((uint32_t)(kb + p), key);
+  s = full ? kb + p : (int64_t)order[kb + p];
+}
+
+// sigma_t of a whole sweep, once per sweep: every product and commit launch
+// of the sweep reads its states from this table instead of evaluating the
+// Feistel network per row (40 Philox rounds of 32-bit multiplies each).
+__global__ void __launch_bounds__(256) multi_order_kernel(MultiArgs A, uint64_t t) {
+  if (multi_done(A.ctl)) return;  // uniform over the launch
+  const OrderKey key = make_order_key(A.n, A.seed, t);
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < A.n;
+       p += (int64_t)gridDim.x * blockDim.x)
+    A.order[p] = (int32_t)sweep_order_at((uint32_t)p, key);
 }
 
 // Partial products of one K-range: part[split][row][j] = sum over k in the
@@ -90,7 +102,6 @@ __global__ void __launch_bounds__(256) multi_gemm_kernel(MultiArgs A, uint64_t t
   const int64_t wg0 = (int64_t)blockIdx.x * 4 * (16 * RT);
   if (wg0 >= rows) return;  // whole workgroup: no barrier is skipped by part of it
   const int64_t tile0 = wg0 + wave * (16 * RT);
-  const OrderKey key = make_order_key(A.n, A.seed, t);
   const int i = lane & 15, g = lane >> 4;
   const int64_t n = A.n;
   const MBDP_GLOBAL uint16_t* P = (const MBDP_GLOBAL uint16_t*)A.P;
@@ -102,7 +113,7 @@ __global__ void __launch_bounds__(256) multi_gemm_kernel(MultiArgs A, uint64_t t
     row = row < rows ? row : rows - 1;  // ragged tile: a valid row, result dropped
     int64_t s;
     int32_t a;
-    multi_row_state(row, A.m, full, kb, key, s, a);
+    multi_row_state(row, A.m, full, kb, A.order, s, a);
     arow[rt] = P + ((size_t)s * A.m + a) * (size_t)n + 8 * g;
   }
   f32x4 acc[RT][NCT];
@@ -201,8 +212,7 @@ __global__ void __launch_bounds__(256) multi_commit_kernel(MultiArgs A, uint64_t
   const int64_t p = blockIdx.x;                // position in the launch (< min(b, n - kb))
   const int AL = 256 / A.r;
   const int al = threadIdx.x / A.r, j = threadIdx.x - al * A.r;
-  const OrderKey key = make_order_key(A.n, A.seed, t);
-  const int64_t s = mode ? kb + p : (int64_t)sweep_order_at((uint32_t)(kb + p), key);
+  const int64_t s = mode ? kb + p : (int64_t)A.order[kb + p];
   double best = INFINITY;
   int32_t besta = 0;
   if (al < AL) {
@@ -388,6 +398,14 @@ int launch_multi_commit(const MultiArgs& a, uint64_t t, int64_t k, int mode, voi
 int launch_multi_end(const MultiArgs& a, void* stream) {
   hipLaunchKernelGGL(multi_end_kernel, dim3(1), dim3(256), 0,
                      reinterpret_cast<hipStream_t>(stream), a);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_multi_order(const MultiArgs& a, uint64_t t, void* stream) {
+  int64_t blocks = (a.n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(multi_order_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(stream), a, t);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -906,6 +906,7 @@ mbdp_status mdp_multi_solve(mbdp_mdp_t h, int32_t r, const float* C, double* V, 
   a.splits = L.splits;
   a.policy = policy;
   a.dvs = reinterpret_cast<double*>(base + L.dvs);
+  a.order = reinterpret_cast<int32_t*>(base + L.order);
   a.ctl = reinterpret_cast<MultiControl*>(base + L.ctl);
   const char* what = nullptr;
   auto ok = [&](int rc, const char* name) {
@@ -924,6 +925,7 @@ mbdp_status mdp_multi_solve(mbdp_mdp_t h, int32_t r, const float* C, double* V, 
   while (launched < max_sweeps) {
     const int64_t chunk = std::min<int64_t>(kMultiChunk, max_sweeps - launched);
     for (int64_t c = 0; c < chunk && !what; ++c, ++t) {
+      ok(launch_multi_order(a, t, stream), "sweep order");
       for (int64_t k = 0; k < nb && !what; ++k) {
         ok(launch_multi_gemm(a, t, k, 0, stream), "product");
         ok(launch_multi_commit(a, t, k, 0, stream), "commit");
