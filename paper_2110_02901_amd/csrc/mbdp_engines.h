@@ -1124,16 +1124,15 @@ struct BandEngine : EllEngine<UNR, LPR, T> {
 // rows of states [B * bs, (B + 1) * bs) (bs * m <= 4096 rows), sorted by
 // column and packed into groups of 64 entries whose rows are distinct, each
 // entry a 32-bit key (column << 12 | row within the block) and an FP32 value
-// (padding entries have value 0).  A workgroup takes a block, its waves take
-// the groups in turn and gather V for a group's 64 columns -- sorted, so
-// they fall on a few cache lines instead of 64 -- then add value * V into
-// the wave's own copy of the block's row sums in LDS (the rows of a group
-// are distinct, so a wave's 64 lanes never collide, and no other wave
-// writes that copy: no atomics).  The copies are summed in a fixed order
-// per row, the cost added in FP64, the minimum taken and committed as by
-// the other engines.  Policy sweeps (one row per state) and b < n use the
-// row-major engine, whose re-centring pass is also used.
-constexpr int kColWaves = 8;     // wavefronts per workgroup, one LDS copy each
+// (padding entries have value 0).  A wavefront takes a block and its groups
+// in order, gathers V for a group's 64 columns -- sorted, so they fall on a
+// few cache lines instead of 64 -- and adds value * V into the block's row
+// sums in its own part of the LDS (the rows of a group are distinct, so a
+// wave's 64 lanes never collide, and no other wave writes there: no
+// atomics).  Then the cost is added in FP64, the minimum taken and
+// committed as by the other engines.  Policy sweeps (one row per state) and
+// b < n use the row-major engine, whose re-centring pass is also used.
+constexpr int kColWaves = 8;     // wavefronts per workgroup, one block's row sums each
 
 struct ColShared {
   float acc[kColWaves][kColRows] __attribute__((aligned(16)));
@@ -1149,8 +1148,16 @@ struct ColEngine : EllEngine<UNR, LPR, ValF32> {
   static constexpr bool kBand = false;
   using Base = EllEngine<UNR, LPR, ValF32>;
   using Acc = typename Base::Acc;
-  static constexpr int U = 8;  // groups of 64 entries in flight per wavefront
+  static constexpr int U = 16;      // groups of 64 entries in flight per wavefront
+  static constexpr int kAlign = 1;  // rounds of U groups between workgroup barriers
 
+  // Each wavefront owns one block of a set of W consecutive blocks (its own
+  // LDS row sums, no copies to add), and the workgroup's wavefronts walk V
+  // in column order side by side: a workgroup barrier every kAlign rounds
+  // keeps them within a few groups of each other, so a V line that one
+  // wavefront brings into the compute unit's L1 is still there when the
+  // others gather from it.  (Without the barriers the wavefronts drift
+  // apart and every gather line goes to L2.)
   template <bool CE, bool IDENT, class Acc>
   __device__ __forceinline__ static void batch(const KParams& p, const int32_t* ord, int64_t bk,
                                                const Ctx& c, int mode, Acc& L) {
@@ -1158,65 +1165,73 @@ struct ColEngine : EllEngine<UNR, LPR, ValF32> {
       Base::template batch<CE, IDENT>(p, ord, bk, c, mode, L);
       return;
     }
-    float(&acc)[kColWaves][kColRows] = col_shared().acc;
     const int m = p.m;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int W = (int)(blockDim.x >> 6);  // <= kColWaves (the launch uses 512 threads)
     const int64_t bs = p.cb_states, n = p.n;
-    const int rows_blk = (int)bs * m;
     const int64_t nblk = (n + bs - 1) / bs;
     const float* __restrict__ rd = c.rd;
-    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-      const int64_t s0 = blk * bs;
-      const int ns = (int)min(bs, n - s0);
-      for (int i = threadIdx.x; i < W * kColRows / 4; i += blockDim.x)
-        reinterpret_cast<f4*>(&acc[0][0])[i] = f4{0.f, 0.f, 0.f, 0.f};
-      __syncthreads();
-      const int64_t g0 = p.cb_gptr[blk], g1 = p.cb_gptr[blk + 1];
-      float* a = acc[wv];
-      for (int64_t gg = g0 + wv; gg < g1; gg += (int64_t)W * U) {
-        uint32_t kk[U];
-        float vv[U], gv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int64_t gr = gg + (int64_t)u * W;
-          const bool ok = gr < g1;
-          const size_t e = (size_t)(ok ? gr : g0) * kWave + lane;  // a valid group either way
-          kk[u] = __builtin_nontemporal_load(p.cb_keys + e);
-          vv[u] = ok ? __builtin_nontemporal_load(p.cb_vals + e) : 0.f;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) gv[u] = rd[kk[u] >> 12];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const uint32_t r = kk[u] & (kColRows - 1);
-          a[r] = fmaf(vv[u], gv[u], a[r]);
-        }
+    float* a = col_shared().acc[wv];
+    for (int64_t set = blockIdx.x; set * W < nblk; set += gridDim.x) {
+      const int64_t blk = set * W + wv;
+      const bool have = blk < nblk;
+      for (int i = lane; i < kColRows / 4; i += kWave)
+        reinterpret_cast<f4*>(a)[i] = f4{0.f, 0.f, 0.f, 0.f};
+      const int64_t g0 = have ? p.cb_gptr[blk] : 0, g1 = have ? p.cb_gptr[blk + 1] : 0;
+      // every wavefront runs as many rounds (and barriers) as the set's
+      // longest block needs
+      int64_t gmax = 0;
+      for (int w = 0; w < W; ++w) {
+        const int64_t b2 = set * W + w;
+        if (b2 < nblk) gmax = max(gmax, (int64_t)(p.cb_gptr[b2 + 1] - p.cb_gptr[b2]));
       }
-      __syncthreads();
-      for (int i = threadIdx.x; i < ns; i += blockDim.x) {
-        const int32_t s = (int32_t)(s0 + i);
-        const float old = rd[s];
-        const double aux = commit_aux<CE, IDENT>(p, s);
-        double qb = INFINITY;
-        int ab = 0;
-        for (int act = 0; act < m; ++act) {
-          const int r = i * m + act;
-          float sum = 0.f;
-          for (int w = 0; w < W; ++w) sum += acc[w][r];
-          const double q = cost_of<CE>(p, (int64_t)s * m + act) + p.gamma * (double)sum;
-          if (q < qb) {  // ascending actions: strictly smaller keeps the lowest
-            qb = q;
-            ab = act;
+      int round = 0;
+      for (int64_t it = 0; it < gmax; it += U, ++round) {
+        if (g0 + it < g1) {
+          uint32_t kk[U];
+          float vv[U], gv[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int64_t gr = g0 + it + u;
+            const bool ok = gr < g1;
+            const size_t e = (size_t)(ok ? gr : g0) * kWave + lane;  // a valid group either way
+            kk[u] = __builtin_nontemporal_load(p.cb_keys + e);
+            vv[u] = ok ? __builtin_nontemporal_load(p.cb_vals + e) : 0.f;
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) gv[u] = rd[kk[u] >> 12];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const uint32_t r = kk[u] & (kColRows - 1);
+            a[r] = fmaf(vv[u], gv[u], a[r]);
           }
         }
-        if (mode >= kModeImprove)
-          commit_improve(p, s, qb, ab, old, mode == kModeImproveCount, aux, L);
-        else
-          commit_sweep(p, c, s, qb, ab, old, aux, L);
+        if (round % kAlign == kAlign - 1) __builtin_amdgcn_s_barrier();
       }
-      __syncthreads();  // the copies are cleared for the next block
-      (void)rows_blk;
+      // the block's states: cost in FP64, minimum, commit (a lane per state)
+      if (have) {
+        const int64_t s0 = blk * bs;
+        const int ns = (int)min(bs, n - s0);
+        for (int i = lane; i < ns; i += kWave) {
+          const int32_t s = (int32_t)(s0 + i);
+          const float old = rd[s];
+          const double aux = commit_aux<CE, IDENT>(p, s);
+          double qb = INFINITY;
+          int ab = 0;
+          for (int act = 0; act < m; ++act) {
+            const double q = cost_of<CE>(p, (int64_t)s * m + act) + p.gamma * (double)a[i * m + act];
+            if (q < qb) {  // ascending actions: strictly smaller keeps the lowest
+              qb = q;
+              ab = act;
+            }
+          }
+          if (mode >= kModeImprove)
+            commit_improve(p, s, qb, ab, old, mode == kModeImproveCount, aux, L);
+          else
+            commit_sweep(p, c, s, qb, ab, old, aux, L);
+        }
+      }
     }
   }
 };
