@@ -84,8 +84,9 @@ __global__ void __launch_bounds__(256) multi_order_kernel(MultiArgs A, uint64_t 
 // once per workgroup with whole-line loads (double buffered: the next
 // round's W is fetched during this round's products).  Reading W per
 // wavefront from L2 in 64-byte pieces cost more than the row stream itself.
-// Rounds are 128 wide up to 32 vectors, 64 wide above (registers).
-template <int RT, int NCT, int ROUND>  // ROUND: K per round (64 or 128)
+// Rounds are 256 wide for 32 vectors, 128 for 16 and 64 above (measured:
+// wider rounds were slower for 16 and 48 vectors; 64 needs the registers).
+template <int RT, int NCT, int ROUND>  // ROUND: K per round (64, 128 or 256)
 __global__ void __launch_bounds__(256) multi_gemm_kernel(MultiArgs A, uint64_t t, int64_t k,
                                                          int full) {
   constexpr int U = ROUND / 32;
@@ -368,7 +369,7 @@ typedef void (*MultiGemmFn)(MultiArgs, uint64_t, int64_t, int);
 static MultiGemmFn multi_gemm_fn(int32_t r) {
   switch (r) {
     case 16: return multi_gemm_kernel<1, 1, 128>;
-    case 32: return multi_gemm_kernel<2, 2, 128>;
+    case 32: return multi_gemm_kernel<2, 2, 256>;
     case 48: return multi_gemm_kernel<3, 3, 64>;
     case 64: return multi_gemm_kernel<4, 4, 64>;
     default: return nullptr;
