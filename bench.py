@@ -180,9 +180,6 @@ def run_multi(args, dev):
     largest change of a sweep over all vectors is <= 1e-8 (so every column is
     within 1e-8 gamma / (1 - gamma) ~ 1e-6 of its J*)."""
     import torch
-    import oracle
-    from oracle import multi as om
-    from oracle import quantize as qz
     from paper_2110_02901_amd import binding as mb
     from paper_2110_02901_amd import inputs
 
@@ -206,7 +203,7 @@ def run_multi(args, dev):
         # counter runs: solves of exactly S and 3S sweeps, each after a fill of V
         out = {"workload": "multi-8192x16", "r": r, "b": b, "launches": [],
                "sources_hash": sources_hash("multi"), "algorithmic_bytes_per_sweep": bytes_sweep}
-        for sweeps in (args.profile_sweeps, 3 * args.profile_sweeps):
+        for sweeps in (args.profile_sweeps, args.profile_sweeps, 3 * args.profile_sweeps):  # warm-up, S, 3S
             V.zero_()
             st = mb.mdp_multi_solve(h, Cd, V, b, seed, ws, tol_dv=-1.0, max_sweeps=sweeps)
             out["launches"].append({"sweeps": st["sweeps"], "recentrings": st["recentrings"]})
@@ -265,6 +262,9 @@ def run_multi(args, dev):
     cpu = None
     if not args.no_cpu_baseline:
         # the oracle's backups of a sample of states against the same stored rows
+        import oracle
+        from oracle import multi as om
+        from oracle import quantize as qz
         try:
             from threadpoolctl import threadpool_info
             cores = max((t.get("num_threads", 1) for t in threadpool_info()), default=1)
@@ -361,7 +361,7 @@ def run_batch(args, dev):
         out = {"workload": "batch-512", "launches": [], "sources_hash": sources_hash("batch"),
                "algorithmic_bytes_per_sweep": float(total_bytes),
                "padded_bytes_per_sweep": float(padded_bytes)}
-        for sweeps in (args.profile_sweeps, 3 * args.profile_sweeps):
+        for sweeps in (args.profile_sweeps, args.profile_sweeps, 3 * args.profile_sweeps):  # warm-up, S, 3S
             for it in items:
                 it["V"].zero_()
             torch.cuda.synchronize()
@@ -514,9 +514,10 @@ def main():
     ap.add_argument("--batch-sizes", default=None,
                     help="comma-separated batch sizes (default: the workload's)")
     ap.add_argument("--eps", type=float, default=1e-6)
-    ap.add_argument("--precision", default="f32", choices=["f32", "bf16", "fp8"],
-                    help="storage of the transition probabilities (BF16 / FP8 rows with one "
-                         "scale per row, quantised on the GPU; the solve targets the stored MDP)")
+    ap.add_argument("--precision", default="f32",
+                    help="storage of the transition probabilities: f32, bf16 or fp8 (BF16 / "
+                         "FP8 rows with one scale per row, quantised on the GPU; the solve "
+                         "targets the stored MDP); with --profile-sweeps, a comma-separated list")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mpi", action="store_true")
@@ -530,6 +531,10 @@ def main():
     if any(w not in workloads for w in names) or (len(names) > 1 and (
             not args.profile_sweeps or any(w in ("batch-512", "multi-8192x16") for w in names))):
         ap.error("--workload: %s" % args.workload)
+    precs = args.precision.split(",")
+    if any(p not in ("f32", "bf16", "fp8") for p in precs) or (
+            len(precs) > 1 and not args.profile_sweeps):
+        ap.error("--precision: %s" % args.precision)
     if args.gpus != 1:
         print("bench.py measures one GPU only: the mini-batch sweep is built and timed on a "
               "single MI355X (sharding over several GPUs is described, not implemented); "
@@ -569,10 +574,12 @@ def main():
     if wl_name == "multi-8192x16":
         run_multi(args, dev)
         return
-    if args.profile_sweeps and "," in wl_name:
-        # counter runs of several workloads in one process (one rocprofv3 run)
-        for name in wl_name.split(","):
-            run_single(args, dev, name)
+    if args.profile_sweeps and len(names) * len(precs) > 1:
+        # counter runs of several workloads / storages in one process (one
+        # rocprofv3 run)
+        for name in names:
+            for prec in precs:
+                run_single(argparse.Namespace(**dict(vars(args), precision=prec)), dev, name)
         return
     run_single(args, dev, wl_name)
 
@@ -654,6 +661,7 @@ def run_single(args, dev, wl_name):
             out["launches"].append({"sweeps": st["sweeps"], "recentrings": st["recentrings"],
                                     "ms": e0.elapsed_time(e1)})
         out["workload"] = wl_name
+        out["precision"] = args.precision
         print(json.dumps(out), flush=True)
         return
 
