@@ -86,6 +86,10 @@ __global__ void __launch_bounds__(256) multi_order_kernel(MultiArgs A, uint64_t 
 // wavefront from L2 in 64-byte pieces cost more than the row stream itself.
 // Rounds are 256 wide for 32 vectors, 128 for 16 and 64 above (measured:
 // wider rounds were slower for 16 and 48 vectors; 64 needs the registers).
+// A row load brings 64 bytes of each of 16 rows (the MFMA operand layout),
+// so each 128-byte line is asked for by two loads of the same wavefront;
+// plain loads, which L1 keeps, serve the second half from the first
+// (non-temporal ones were 1-7% slower).
 template <int RT, int NCT, int ROUND>  // ROUND: K per round (64, 128 or 256)
 __global__ void __launch_bounds__(256) multi_gemm_kernel(MultiArgs A, uint64_t t, int64_t k,
                                                          int full) {
@@ -160,8 +164,7 @@ __global__ void __launch_bounds__(256) multi_gemm_kernel(MultiArgs A, uint64_t t
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
-        av[u][rt] = u < steps ? __builtin_nontemporal_load(
-                                    (const MBDP_GLOBAL u32x4*)(arow[rt] + kk + 32 * u))
+        av[u][rt] = u < steps ? *(const MBDP_GLOBAL u32x4*)(arow[rt] + kk + 32 * u)
                               : u32x4{0u, 0u, 0u, 0u};
     const bool next = kk + ROUND < k1;
     u32x4 wr[WPER];
