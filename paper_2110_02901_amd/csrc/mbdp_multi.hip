@@ -66,11 +66,19 @@ __device__ __forceinline__ void multi_row_state(int64_t row, int32_t m, int full
 // sigma_t of a whole sweep, once per sweep: every product and commit launch
 // of the sweep reads its states from this table instead of evaluating the
 // Feistel network per row (40 Philox rounds of 32-bit multiplies each).
+// A wavefront runs its cycle walk until its slowest lane is done, so only
+// kMultiOrderLanes lanes of each take a position (the expected longest of 16
+// walks is about 5 Feistel passes, of 64 about 7) and the positions spread
+// over four times as many wavefronts.
+constexpr int kMultiOrderLanes = 16;
 __global__ void __launch_bounds__(256) multi_order_kernel(MultiArgs A, uint64_t t) {
   if (multi_done(A.ctl)) return;  // uniform over the launch
+  if ((threadIdx.x & 63) >= kMultiOrderLanes) return;
   const OrderKey key = make_order_key(A.n, A.seed, t);
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < A.n;
-       p += (int64_t)gridDim.x * blockDim.x)
+  const int64_t lane_id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64 * kMultiOrderLanes +
+                          (threadIdx.x & 63);
+  const int64_t lanes = (int64_t)gridDim.x * (blockDim.x / 64) * kMultiOrderLanes;
+  for (int64_t p = lane_id; p < A.n; p += lanes)
     A.order[p] = (int32_t)sweep_order_at((uint32_t)p, key);
 }
 
@@ -211,12 +219,20 @@ __global__ void __launch_bounds__(256) multi_commit_kernel(MultiArgs A, uint64_t
                                                            int mode) {
   __shared__ double qs[256];
   __shared__ int32_t as[256];
-  if (mode == 0 && multi_done(A.ctl)) return;  // uniform over the launch
   const int64_t kb = k * A.b;
   const int64_t p = blockIdx.x;                // position in the launch (< min(b, n - kb))
   const int AL = 256 / A.r;
   const int al = threadIdx.x / A.r, j = threadIdx.x - al * A.r;
-  const int64_t s = mode ? kb + p : (int64_t)A.order[kb + p];
+  // The stop flag is requested with the state (the table is read in either
+  // mode, so neither load waits behind a branch) and tested only before the
+  // first store; the state's old W and R are requested with its costs.
+  const unsigned done = __hip_atomic_load(&A.ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int64_t o = A.order[kb + p];
+  const bool stop = mode == 0 && done != 0u;
+  const int64_t s = mode ? kb + p : o;
+  const size_t e = (size_t)s * A.r + j;
+  const bool commit = mode == 0 && al == 0;
+  const double w_old = commit ? A.W[e] : 0.0, r_old = commit ? A.R[e] : 0.0;
   double best = INFINITY;
   int32_t besta = 0;
   if (al < AL) {
@@ -238,6 +254,7 @@ __global__ void __launch_bounds__(256) multi_commit_kernel(MultiArgs A, uint64_t
   qs[threadIdx.x] = best;
   as[threadIdx.x] = besta;
   __syncthreads();
+  if (stop) return;  // uniform over the launch; nothing was stored
   double dv = 0.0;
   if (al == 0) {
     for (int l = 1; l < AL; ++l) {
@@ -249,11 +266,10 @@ __global__ void __launch_bounds__(256) multi_commit_kernel(MultiArgs A, uint64_t
       }
     }
     if (mode == 1) {
-      A.policy[(size_t)s * A.r + j] = besta;
+      A.policy[e] = besta;
     } else {
-      const size_t e = (size_t)s * A.r + j;
-      const double wnew = best - A.R[e];
-      dv = fabs(wnew - A.W[e]);
+      const double wnew = best - r_old;
+      dv = fabs(wnew - w_old);
       A.W[e] = wnew;
       const unsigned hi = multi_bf16_rne((float)wnew);
       const unsigned lo = multi_bf16_rne((float)(wnew - (double)__uint_as_float(hi << 16)));
@@ -275,6 +291,7 @@ __global__ void __launch_bounds__(256) multi_end_kernel(MultiArgs A) {
   __shared__ double red[4];
   if (multi_done(A.ctl)) return;  // uniform over the workgroup
   double dv = 0.0;
+#pragma unroll 8  // independent loads, so several are in flight
   for (int64_t e = threadIdx.x; e < A.n; e += blockDim.x) dv = fmax(dv, A.dvs[e]);
   dv = wave_max_d(dv);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dv;
@@ -406,7 +423,8 @@ int launch_multi_end(const MultiArgs& a, void* stream) {
 }
 
 int launch_multi_order(const MultiArgs& a, uint64_t t, void* stream) {
-  int64_t blocks = (a.n + 255) / 256;
+  const int64_t per_block = 4 * kMultiOrderLanes;  // positions per 256-thread workgroup and pass
+  int64_t blocks = (a.n + per_block - 1) / per_block;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(multi_order_kernel, dim3((unsigned)blocks), dim3(256), 0,
                      reinterpret_cast<hipStream_t>(stream), a, t);
