@@ -94,6 +94,27 @@ def test_mpi_reaches_eps_and_stops_on_its_rule(uni3000):
     assert np.max(np.abs(V64.cpu().numpy() - Vstar)) <= 1e-10 / (1 - 0.995) + 1e-9
 
 
+@pytest.mark.parametrize("n", [3000, 50000])
+def test_repeated_solves_are_bit_identical(n):
+    """The kernel's arithmetic does not depend on timing: each block's row
+    sums are kept by one wavefront and the workgroup barriers only pace the
+    wavefronts, so two solves of 40 sweeps give the same bits (n = 50 000:
+    98 blocks, the last set of 8 holds 2)."""
+    rp, col, val, c = inputs.csr_mdp(n, 8, 32, 1.0, 36, band=None)
+    h, _ = csr_case(rp, col, val, c, 0.995)
+    mb.mdp_column_blocks(h)
+    mb.mdp_set_tuning(h, band_window=-1)
+    assert mb.mdp_engine(h, n) == "ell-colblock"
+    ws = mb.workspace(h, n)
+    out = []
+    for _ in range(2):
+        V = torch.zeros(n, dtype=torch.float32, device=dev())
+        st = mb.vi_solve(h, V, n, 7, ws, tol_dv=-1.0, max_sweeps=40)
+        assert st["sweeps"] == 40
+        out.append(V.cpu().numpy())
+    assert np.array_equal(out[0].view(np.uint32), out[1].view(np.uint32))
+
+
 def test_same_iterates_as_the_row_major_kernel():
     """Two handles on the same arrays, one with column blocks: 50 sweeps of
     VI at b = n agree within FP32 rounding of the sums."""

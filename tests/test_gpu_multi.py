@@ -69,6 +69,18 @@ def test_sweeps_match_oracle(r, b):
         check_argmin(Q[:, :, j], pol[:, j], 1e-9)
 
 
+def test_repeated_solves_are_bit_identical():
+    """The split partial sums are added in split order by one thread per
+    (state, vector), so two solves give the same bits (policies too)."""
+    n, m, r, b = 512, 4, 32, 64
+    h, _, C = bf16_case(n, m, r, 0.95, 41)
+    V0 = np.zeros((n, r))
+    runs = [gpu_multi(h, C, V0, b, 9, max_sweeps=30) for _ in range(2)]
+    assert runs[0][2]["sweeps"] == runs[1][2]["sweeps"] == 30
+    assert np.array_equal(runs[0][0].view(np.uint64), runs[1][0].view(np.uint64))
+    assert np.array_equal(runs[0][1], runs[1][1])
+
+
 def test_ragged_and_tiny_shapes():
     for (n, m, r, b) in ((32, 1, 16, 1), (96, 3, 48, 17), (160, 5, 32, 160), (64, 7, 64, 9)):
         h, Pst, C = bf16_case(n, m, r, 0.85, 20 + n)
