@@ -281,8 +281,10 @@ mbdp_status mdp_multi_solve(mbdp_mdp_t h, int32_t r, const float* C, double* V, 
  * from before it (eq. (11) with an empty updated set: the Bellman operator T,
  * eq. (7)), so a backup's products may be summed in any order.  For a
  * constant-row-length FP32 MDP with n <= 2^20 states (and m <= 4096) the
- * library can keep a second copy of the entries, grouped by blocks of
- * 4096 / m states and sorted by column inside each block, packed into groups
+ * library can keep a second copy of the entries, grouped by blocks of at
+ * most 4096 / m states (fewer, down to half that, so that the blocks fill
+ * whole passes of the device's compute units, 8 blocks to a compute unit)
+ * and sorted by column inside each block, packed into groups
  * of 64 entries with distinct rows (padding entries have value 0): the V
  * gathers of a wavefront then fall on a few cache lines instead of 64, and
  * the products are summed in LDS without atomics.  Solves and sweeps with
